@@ -1,0 +1,184 @@
+/*
+ * ifgf.h -- C ABI of libifgf.so, the MI355X (gfx950) implementation of the
+ * Interpolated Factored Green Function (IFGF) evaluation of the discrete
+ * Helmholtz operator (Bauinger & Bruno, "Massively parallelized interpolated
+ * factored Green function method", Section 2, eq. (field1)):
+ *
+ *     out_l = sum_{m != l} a_m exp(i kappa |x_l - x_m|) / (4 pi |x_l - x_m|),
+ *     l = 1..N.
+ *
+ * Sign e^{+i kappa r}, the factor 1/(4 pi) included, the self term excluded.
+ *
+ * Conventions for every entry point:
+ *   - Plain C types only; no C++ exception crosses the boundary.
+ *   - Every function returns an ifgf_status; on error nothing is written to
+ *     the caller's output and ifgf_status_string() describes the failure
+ *     (for IFGF_EHIP it includes the HIP error of the failing call).
+ *   - Points are FP64, N x 3 row-major, in HOST memory.  Densities and
+ *     outputs are DEVICE pointers on the plan's GPU.
+ *   - Complex numbers are interleaved (re, im): complex128 (two doubles) in
+ *     IFGF_FP64 mode, complex64 (two floats) in IFGF_FP32_MIXED mode.
+ *   - Densities and outputs are laid out [n_rhs][N] in the caller's point
+ *     order (RHS-major, point index fastest).
+ */
+#ifndef IFGF_H
+#define IFGF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ifgf_plan_s* ifgf_plan_t; /* opaque, owned by the library */
+
+typedef enum {
+  IFGF_OK = 0,
+  IFGF_EINVAL = 1,      /* n < 2, kappa <= 0, p < 1, NaN/Inf coordinates,
+                           bad options, null pointers */
+  IFGF_ENOMEM = 2,      /* host or device allocation failed */
+  IFGF_EDUPLICATE = 3,  /* two identical points: eq. (field1) is singular */
+  IFGF_EHIP = 4,        /* a HIP runtime call failed */
+  IFGF_EUNSUPPORTED = 5,/* (p_s, p_ang) without a compiled kernel, N >= 2^31,
+                           too many levels */
+  IFGF_ELOOKUP = 6      /* a cone look-up missed during apply (internal
+                           consistency error; reported by ifgf_check) */
+} ifgf_status;
+
+typedef enum { IFGF_FP64 = 0, IFGF_FP32_MIXED = 1 } ifgf_precision;
+
+/* Options of a plan.  Obtain defaults with ifgf_default_opts(). */
+typedef struct ifgf_opts {
+  int precision;    /* ifgf_precision.  IFGF_FP32_MIXED: interpolation,
+                       propagation and near field in FP32 complex; point and
+                       box-centre geometry, cone selection, the phase
+                       kappa*|x - x_c| (argument reduction) and the
+                       centred-factor ratio in FP64. */
+  int n_rhs;        /* number of right-hand sides per apply, >= 1 */
+  int leaf_grid[3]; /* cone-segment grid (n_s, n_theta, n_phi) at the leaf
+                       level D; each level up doubles every dimension.
+                       {0,0,0} selects the default {2,4,8}. */
+  int levels;       /* number of octree levels D; 0 selects
+                       D = max(3, 1 + round(log2(H_1 / (leaf_size lambda)))) */
+  int stages;       /* bit 0: near field (level-D neighbours, direct sum);
+                       bit 1: far field (IFGF levels D..3).  0 means both. */
+  int host_only;    /* 1: build the host octree only (no GPU used); only
+                       ifgf_plan_info and ifgf_partition_counts may be
+                       called on such a plan */
+  int device;       /* HIP device ordinal; -1 uses the current device */
+  void* stream;     /* hipStream_t used by ifgf_apply; NULL = null stream */
+} ifgf_opts;
+
+/* Size information about a plan (ifgf_plan_info). */
+#define IFGF_MAX_LEVELS 24
+typedef struct ifgf_info {
+  int64_t n_points;       /* total points (all instances) */
+  int n_instances;
+  int max_levels;         /* max D over instances */
+  int n_steps;            /* levels >= 3 handled on the GPU (= max D - 2) */
+  int p_s, p_ang, n_rhs, precision;
+  /* Per step l = D - d (l = 0 is the leaf level), summed over instances: */
+  int64_t boxes[IFGF_MAX_LEVELS];      /* relevant boxes */
+  int64_t cones[IFGF_MAX_LEVELS];      /* relevant cone segments */
+  int64_t cousin_pairs[IFGF_MAX_LEVELS]; /* (target, cousin box) pairs */
+  int64_t grid[IFGF_MAX_LEVELS];       /* cone grid size per box */
+  int64_t prop_pairs[IFGF_MAX_LEVELS]; /* (parent-cone node, relevant child)
+                                         evaluations of Propagation into
+                                         step l (l >= 1) */
+  int64_t leaf_pairs;     /* (leaf-cone node, source) evaluations of
+                             LevelDEvaluations */
+  int64_t near_pairs;     /* (target, source) near-field pairs, self included */
+  int64_t device_bytes;   /* device memory held by the plan */
+  double plan_seconds;    /* wall time of plan construction */
+} ifgf_info;
+
+/* Fill *opts with the defaults: FP64, 1 RHS, leaf grid {2,4,8}, automatic
+ * D, both stages, device -1, null stream. */
+ifgf_status ifgf_default_opts(ifgf_opts* opts);
+
+/* Plan one instance (Section 2 of the paper: octree, relevant boxes,
+ * neighbour and cousin lists, relevant cone segments; Morton ordering of
+ * Section 3.2).  points: N x 3 FP64 host array, copied.  kappa > 0.
+ * p_s, p_ang: Chebyshev points per cone in the radial and in each angular
+ * variable (P = p_s * p_ang^2 interpolation points per cone); compiled
+ * kernels exist for (3,5), (2,3) and (5,7).  leaf_size: leaf box side in
+ * wavelengths (0.25 is typical).  Uses default options. */
+ifgf_status ifgf_plan(ifgf_plan_t* plan, const double* points, int64_t n,
+                      double kappa, int p_s, int p_ang, double leaf_size);
+
+/* As ifgf_plan with explicit options (opts may be NULL for defaults). */
+ifgf_status ifgf_plan_ex(ifgf_plan_t* plan, const double* points, int64_t n,
+                         double kappa, int p_s, int p_ang, double leaf_size,
+                         const ifgf_opts* opts);
+
+/* Plan n_inst independent instances evaluated together by every apply
+ * (each kernel launch processes all instances).  Instance i owns points
+ * [offsets[i], offsets[i+1]) of the host array `points` (offsets has n_inst+1
+ * entries, offsets[0] = 0), wavenumber kappas[i].  Densities and outputs of
+ * a batched apply are [n_rhs][N_total], N_total = offsets[n_inst], in that
+ * concatenated order.  Interactions never cross instances. */
+ifgf_status ifgf_plan_batched(ifgf_plan_t* plan, int n_inst,
+                              const int64_t* offsets, const double* points,
+                              const double* kappas, int p_s, int p_ang,
+                              double leaf_size, const ifgf_opts* opts);
+
+/* Evaluate out = A(densities) (eq. (field1)) on the plan's stream.
+ * densities, out: device pointers, [n_rhs][N] interleaved complex of the
+ * plan's precision (complex128 for IFGF_FP64, complex64 for
+ * IFGF_FP32_MIXED); out is overwritten.  Asynchronous with respect to the
+ * host; one apply at a time per plan (not re-entrant). */
+ifgf_status ifgf_apply(ifgf_plan_t plan, const void* densities, void* out);
+
+/* Wait for the plan's stream and report whether any cone look-up of the
+ * previous applies missed (IFGF_ELOOKUP); clears the flag. */
+ifgf_status ifgf_check(ifgf_plan_t plan);
+
+/* Change the stream used by later applies (hipStream_t; NULL = null stream). */
+ifgf_status ifgf_set_stream(ifgf_plan_t plan, void* hip_stream);
+
+/* Kernel stages timed by the profiler. */
+typedef enum {
+  IFGF_STAGE_PERMUTE_IN = 0,
+  IFGF_STAGE_NEAR_FIELD = 1,
+  IFGF_STAGE_LEAF = 2,          /* LevelDEvaluations */
+  IFGF_STAGE_INTERPOLATION = 3, /* Interpolation(d), all levels */
+  IFGF_STAGE_PROPAGATION = 4,   /* Propagation(d), all levels */
+  IFGF_STAGE_PERMUTE_OUT = 5,
+  IFGF_N_STAGES = 6
+} ifgf_stage;
+
+typedef struct ifgf_stage_times {
+  double ms[IFGF_N_STAGES];        /* summed kernel durations (HIP events) */
+  int64_t launches[IFGF_N_STAGES]; /* kernel launches timed */
+} ifgf_stage_times;
+
+/* Enable (1) or disable (0) timing of every kernel launch of later applies
+ * with HIP events recorded on the plan's stream around each launch. */
+ifgf_status ifgf_profile(ifgf_plan_t plan, int enable);
+
+/* Wait for the plan's stream, add up the timed launches since the last
+ * reset into *times, and reset the accumulators if reset != 0. */
+ifgf_status ifgf_profile_read(ifgf_plan_t plan, ifgf_stage_times* times,
+                              int reset);
+
+/* Sizes and counts of the plan. */
+ifgf_status ifgf_plan_info(ifgf_plan_t plan, ifgf_info* info);
+
+/* Per point (caller order): the number of sources covered by the near-field
+ * neighbour boxes (itself included) plus the points of every cousin box of
+ * levels D..3.  Equals the instance's N for every point (the partition of
+ * the sources of Section 2).  counts: host array of N_total int64. */
+ifgf_status ifgf_partition_counts(ifgf_plan_t plan, int64_t* counts);
+
+/* Release all memory of the plan (host and device).  NULL is ignored. */
+void ifgf_destroy(ifgf_plan_t plan);
+
+/* Human-readable text for a status, including the last HIP error text for
+ * IFGF_EHIP.  Never NULL. */
+const char* ifgf_status_string(ifgf_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IFGF_H */

@@ -1,0 +1,557 @@
+// ifgf_api.cpp -- the C ABI of libifgf.so (declared in include/ifgf.h).
+//
+// Plan construction: host octree and interaction lists (host_tree.cpp),
+// upload, then the relevant cone segments of eq. (relevantconesegments)
+// built on the GPU top-down (level 3 first, i.e. the highest step first):
+// a cone of box k is relevant if it holds a cousin point of k or a node of
+// a relevant cone of k's parent.  Apply: permute in, near field, leaf
+// evaluations, then per level interpolation and propagation, permute out.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/ifgf.h"
+#include "host_tree.h"
+#include "ifgf_device.h"
+
+using namespace ifgf;
+
+namespace {
+
+thread_local std::string g_err;
+
+const double kPi = 3.14159265358979323846;
+
+ifgf_status fail(ifgf_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+struct HipError {
+  hipError_t e;
+  const char* what;
+};
+
+#define HIP_TRY(call)                                   \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) throw HipError{e_, #call};    \
+  } while (0)
+
+}  // namespace
+
+struct ifgf_plan_s {
+  int p_s = 0, p_ang = 0;
+  ifgf_opts opts{};
+  Merged m;
+  ifgf_info info{};
+  // Device state.
+  int device = -1;
+  hipStream_t stream = nullptr;
+  std::vector<void*> allocs;
+  int64_t bytes = 0;
+  ApplyArgs A{};
+  std::vector<StepDev> steps_h;
+  StepDev* steps_d = nullptr;
+  bool device_ready = false;
+  // Profiling.
+  bool profiling = false;
+  std::vector<Profiler::Rec> prof_recs;
+  int prof_pending = 0;
+  double prof_ms[IFGF_N_STAGES] = {0};
+  int64_t prof_launches[IFGF_N_STAGES] = {0};
+
+  template <class T>
+  T* dalloc(int64_t count) {
+    if (count <= 0) count = 1;
+    void* p = nullptr;
+    size_t nbytes = sizeof(T) * (size_t)count;
+    hipError_t e = hipMalloc(&p, nbytes);
+    if (e != hipSuccess) throw HipError{e, "hipMalloc"};
+    allocs.push_back(p);
+    bytes += (int64_t)nbytes;
+    return (T*)p;
+  }
+  template <class T>
+  T* upload(const std::vector<T>& v) {
+    T* p = dalloc<T>((int64_t)v.size());
+    if (!v.empty())
+      HIP_TRY(hipMemcpy(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+    return p;
+  }
+  void dfree(void* p) {
+    auto it = std::find(allocs.begin(), allocs.end(), p);
+    if (it != allocs.end()) allocs.erase(it);
+    (void)hipFree(p);
+  }
+  ~ifgf_plan_s() {
+    for (void* p : allocs) (void)hipFree(p);
+    for (auto& r : prof_recs) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+  }
+};
+
+static ifgf_status validate(int p_s, int p_ang, const ifgf_opts& o) {
+  if (p_s < 1 || p_ang < 1) return fail(IFGF_EINVAL, "p_s and p_ang must be >= 1");
+  if (o.precision != IFGF_FP64 && o.precision != IFGF_FP32_MIXED)
+    return fail(IFGF_EINVAL, "unknown precision");
+  if (o.n_rhs < 1) return fail(IFGF_EINVAL, "n_rhs must be >= 1");
+  if (o.n_rhs > kMaxRhs) return fail(IFGF_EUNSUPPORTED, "n_rhs > 4 is not supported");
+  for (int a = 0; a < 3; ++a)
+    if (o.leaf_grid[a] < 1 || o.leaf_grid[a] > 4096)
+      return fail(IFGF_EINVAL, "leaf_grid entries must be in [1, 4096]");
+  if (o.levels != 0 && o.levels < 3) return fail(IFGF_EINVAL, "levels must be 0 or >= 3");
+  if (o.stages < 0 || o.stages > 3) return fail(IFGF_EINVAL, "stages must be in [0, 3]");
+  bool ok = (p_s == 3 && p_ang == 5) || (p_s == 2 && p_ang == 3) || (p_s == 5 && p_ang == 7);
+  if (!ok && !o.host_only)
+    return fail(IFGF_EUNSUPPORTED, "no kernel compiled for this (p_s, p_ang)");
+  return IFGF_OK;
+}
+
+static uint64_t next_pow2(uint64_t v) {
+  uint64_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+static int bits_for(uint64_t v) {
+  int b = 1;
+  while (b < 64 && (uint64_t(1) << b) <= v) ++b;
+  return b;
+}
+
+// Chebyshev first-kind nodes and Lagrange product weights.
+static void cheb_nodes(int n, double* t, double* w) {
+  for (int j = 0; j < n; ++j) t[j] = std::cos((2.0 * j + 1.0) * kPi / (2.0 * n));
+  for (int j = 0; j < n; ++j) {
+    double p = 1.0;
+    for (int m = 0; m < n; ++m)
+      if (m != j) p *= (t[j] - t[m]);
+    w[j] = 1.0 / p;
+  }
+}
+
+static void build_device(ifgf_plan_s* P) {
+  Merged& m = P->m;
+  const int ps = P->p_s, pa = P->p_ang, PP = ps * pa * pa;
+  const int L = m.n_steps;
+  hipStream_t st = P->stream;
+  ApplyArgs& A = P->A;
+  A.n = m.n;
+  A.nrhs = P->opts.n_rhs;
+  A.n_steps = L;
+  A.stages = P->opts.stages == 0 ? 3 : P->opts.stages;
+  A.x = P->upload(m.xs[0]);
+  A.y = P->upload(m.xs[1]);
+  A.z = P->upload(m.xs[2]);
+  A.perm = P->upload(m.perm);
+  A.inst_kappa = P->upload(m.inst_kappa);
+  A.nbr_begin = P->upload(m.nbr_begin);
+  A.nbr = P->upload(m.nbr);
+  std::memset(&A.cheb, 0, sizeof(A.cheb));
+  cheb_nodes(ps, A.cheb.ts, A.cheb.ws);
+  cheb_nodes(pa, A.cheb.ta, A.cheb.wa);
+  A.err = P->dalloc<int>(1);
+  HIP_TRY(hipMemset(A.err, 0, sizeof(int)));
+
+  const double eta = std::sqrt(3.0) / 3.0;
+  P->steps_h.assign(L, StepDev{});
+  for (int l = 0; l < L; ++l) {
+    MergedStep& S = m.step[l];
+    StepDev& D = P->steps_h[l];
+    D.nb = S.nb;
+    D.center = P->upload(S.center);
+    D.inst = P->upload(S.inst);
+    D.first = P->upload(S.first);
+    D.count = P->upload(S.count);
+    D.child = l >= 1 ? P->upload(S.child) : nullptr;
+    D.cous_begin = P->upload(S.cous_begin);
+    D.cous = P->upload(S.cous);
+    D.pt_box = P->upload(S.pt_box);
+    D.inst_h = P->upload(S.inst_h);
+    // Cone grid: leaf grid doubled per dimension for every level up.
+    D.ns = P->opts.leaf_grid[0] << l;
+    D.nt = P->opts.leaf_grid[1] << l;
+    D.np = P->opts.leaf_grid[2] << l;
+    D.ngrid = (int64_t)D.ns * D.nt * D.np;
+    D.ds = eta / D.ns;
+    D.dt = kPi / D.nt;
+    D.dp = 2.0 * kPi / D.np;
+    std::vector<double> sn((size_t)D.ns * ps), tn((size_t)D.nt * pa * 2), pn((size_t)D.np * pa * 2);
+    for (int i = 0; i < D.ns; ++i)
+      for (int a = 0; a < ps; ++a)
+        sn[(size_t)i * ps + a] = D.ds * (double(i) + 0.5 * (A.cheb.ts[a] + 1.0));
+    for (int i = 0; i < D.nt; ++i)
+      for (int b = 0; b < pa; ++b) {
+        double th = D.dt * (double(i) + 0.5 * (A.cheb.ta[b] + 1.0));
+        tn[2 * ((size_t)i * pa + b)] = std::sin(th);
+        tn[2 * ((size_t)i * pa + b) + 1] = std::cos(th);
+      }
+    for (int i = 0; i < D.np; ++i)
+      for (int c = 0; c < pa; ++c) {
+        double ph = D.dp * (double(i) + 0.5 * (A.cheb.ta[c] + 1.0));
+        pn[2 * ((size_t)i * pa + c)] = std::sin(ph);
+        pn[2 * ((size_t)i * pa + c) + 1] = std::cos(ph);
+      }
+    D.s_node = P->upload(sn);
+    D.t_node = P->upload(tn);
+    D.p_node = P->upload(pn);
+    D.ncones = 0;
+  }
+  P->steps_d = P->dalloc<StepDev>(std::max(L, 1));
+  A.step = P->steps_d;
+  A.step_host = P->steps_h.data();
+  auto sync_steps = [&]() {
+    HIP_TRY(hipMemcpy(P->steps_d, P->steps_h.data(), sizeof(StepDev) * L,
+                      hipMemcpyHostToDevice));
+  };
+  sync_steps();
+
+  // Relevant cones, top-down.
+  unsigned int* counters = P->dalloc<unsigned int>(2);
+  int* overflow = P->dalloc<int>(1);
+  for (int l = L - 1; l >= 0; --l) {
+    StepDev& D = P->steps_h[l];
+    // Unique (box, cone) keys are bounded by the grid, and in practice by
+    // ~2 per (box, cousin box) pair plus a few per parent cone.
+    int64_t pairs = (int64_t)m.step[l].cous.size();
+    uint64_t est = (uint64_t)std::min<double>(
+        (double)D.nb * (double)D.ngrid,
+        2.0 * (double)pairs +
+            (l + 1 < L ? (double)P->steps_h[l + 1].ncones * 8.0 : 0.0) + 4096.0);
+    uint64_t cap = next_pow2(std::max<uint64_t>(4096, 2 * est));
+    unsigned long long* tab = nullptr;
+    unsigned int count = 0;
+    for (int attempt = 0;; ++attempt) {
+      tab = P->dalloc<unsigned long long>((int64_t)cap);
+      HIP_TRY(launch_fill_u64(tab, (int64_t)cap, kEmptyKey, st));
+      HIP_TRY(hipMemsetAsync(counters, 0, 2 * sizeof(unsigned int), st));
+      HIP_TRY(hipMemsetAsync(overflow, 0, sizeof(int), st));
+      MarkArgs M{tab, (unsigned long long)(cap - 1), counters, overflow, 1e-9};
+      HIP_TRY(launch_mark(A, l, ps, pa, M, st));
+      int ovf = 0;
+      HIP_TRY(hipMemcpyAsync(&count, counters, sizeof(unsigned int), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipMemcpyAsync(&ovf, overflow, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      if (!ovf && (double)count <= 0.75 * (double)cap) break;
+      P->dfree(tab);
+      cap *= 4;
+      if (attempt > 8) throw HipError{hipErrorOutOfMemory, "relevant-cone table"};
+    }
+    // Sorted keys -> slots; final lookup table at <= 50% load.
+    unsigned long long* keys = P->dalloc<unsigned long long>(count);
+    unsigned long long* tmp = P->dalloc<unsigned long long>(count);
+    HIP_TRY(hipMemsetAsync(counters + 1, 0, sizeof(unsigned int), st));
+    HIP_TRY(launch_compact(tab, (int64_t)cap, keys, counters + 1, st));
+    P->dfree(tab);
+    if (count > 0) {
+      size_t sbytes = 0;
+      int end_bit = bits_for((uint64_t)D.nb * (uint64_t)D.ngrid);
+      HIP_TRY(sort_keys(keys, tmp, count, end_bit, nullptr, &sbytes, st));
+      void* scratch = P->dalloc<char>((int64_t)sbytes + 16);
+      HIP_TRY(sort_keys(keys, tmp, count, end_bit, scratch, &sbytes, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      P->dfree(scratch);
+    }
+    P->dfree(tmp);
+    uint64_t cap2 = next_pow2(std::max<uint64_t>(1024, 2 * (uint64_t)count));
+    unsigned long long* hk = P->dalloc<unsigned long long>((int64_t)cap2);
+    int* hv = P->dalloc<int>((int64_t)cap2);
+    HIP_TRY(launch_fill_u64(hk, (int64_t)cap2, kEmptyKey, st));
+    HIP_TRY(hipMemsetAsync(overflow, 0, sizeof(int), st));
+    HIP_TRY(launch_build_lookup(keys, count, hk, hv, cap2 - 1, overflow, st));
+    int ovf = 0;
+    HIP_TRY(hipMemcpyAsync(&ovf, overflow, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (ovf) throw HipError{hipErrorUnknown, "cone lookup table overflow"};
+    // Work counts of this step (for throughput and roofline figures).
+    {
+      std::vector<unsigned long long> hkeys(count);
+      if (count > 0)
+        HIP_TRY(hipMemcpy(hkeys.data(), keys, sizeof(unsigned long long) * count,
+                          hipMemcpyDeviceToHost));
+      const MergedStep& S = m.step[l];
+      int64_t pairs_l = 0;
+      for (unsigned long long k : hkeys) {
+        int64_t b = (int64_t)(k / (unsigned long long)D.ngrid);
+        if (l == 0) {
+          pairs_l += (int64_t)PP * S.count[b];
+        } else {
+          int nch = 0;
+          for (int o = 0; o < 8; ++o) nch += S.child[8 * b + o] >= 0;
+          pairs_l += (int64_t)PP * nch;
+        }
+      }
+      if (l == 0) P->info.leaf_pairs = pairs_l;
+      else P->info.prop_pairs[l] = pairs_l;
+    }
+    D.ncones = count;
+    D.cone_key = keys;
+    D.hkey = hk;
+    D.hval = hv;
+    D.hmask = cap2 - 1;
+    sync_steps();
+  }
+
+  // Value buffers (two consecutive levels), sorted densities and output.
+  size_t csize = P->opts.precision == IFGF_FP64 ? 16 : 8;
+  int64_t maxc = 1;
+  for (int l = 0; l < L; ++l) maxc = std::max<int64_t>(maxc, P->steps_h[l].ncones);
+  int64_t vbytes = maxc * A.nrhs * PP * (int64_t)csize;
+  A.vbuf[0] = P->dalloc<char>(vbytes);
+  A.vbuf[1] = P->dalloc<char>(vbytes);
+  A.dens_sorted = P->dalloc<char>(m.n * A.nrhs * (int64_t)csize);
+  A.out_sorted = P->dalloc<char>(m.n * A.nrhs * (int64_t)csize);
+  HIP_TRY(hipStreamSynchronize(st));
+  P->device_ready = true;
+}
+
+static void fill_info(ifgf_plan_s* P) {
+  ifgf_info& I = P->info;
+  Merged& m = P->m;
+  I.n_points = m.n;
+  I.n_instances = m.n_inst;
+  I.max_levels = m.max_D;
+  I.n_steps = m.n_steps;
+  I.p_s = P->p_s;
+  I.p_ang = P->p_ang;
+  I.n_rhs = P->opts.n_rhs;
+  I.precision = P->opts.precision;
+  for (int l = 0; l < m.n_steps && l < IFGF_MAX_LEVELS; ++l) {
+    I.boxes[l] = m.step[l].nb;
+    I.cones[l] = P->device_ready ? P->steps_h[l].ncones : 0;
+    int64_t pairs = 0;
+    for (int64_t b = 0; b < m.step[l].nb; ++b)
+      pairs += (m.step[l].cous_begin[b + 1] - m.step[l].cous_begin[b]) * (int64_t)m.step[l].count[b];
+    I.cousin_pairs[l] = pairs;
+    I.grid[l] = (int64_t)(P->opts.leaf_grid[0] << l) * (P->opts.leaf_grid[1] << l) *
+                (P->opts.leaf_grid[2] << l);
+  }
+  I.near_pairs = m.near_pairs;
+  I.device_bytes = P->bytes;
+}
+
+static ifgf_status plan_common(ifgf_plan_t* out, int n_inst,
+                               const int64_t* offsets, const double* points,
+                               const double* kappas, int p_s, int p_ang,
+                               double leaf_size, const ifgf_opts* opts_in) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!out || !points || !kappas || !offsets) return fail(IFGF_EINVAL, "null pointer");
+  *out = nullptr;
+  if (n_inst < 1) return fail(IFGF_EINVAL, "n_inst must be >= 1");
+  ifgf_opts o;
+  ifgf_default_opts(&o);
+  if (opts_in) o = *opts_in;
+  if (o.leaf_grid[0] == 0 && o.leaf_grid[1] == 0 && o.leaf_grid[2] == 0) {
+    o.leaf_grid[0] = 2;
+    o.leaf_grid[1] = 4;
+    o.leaf_grid[2] = 8;
+  }
+  ifgf_status s = validate(p_s, p_ang, o);
+  if (s != IFGF_OK) return s;
+  if (offsets[0] != 0) return fail(IFGF_EINVAL, "offsets[0] must be 0");
+  for (int i = 0; i < n_inst; ++i)
+    if (offsets[i + 1] - offsets[i] < 2) return fail(IFGF_EINVAL, "every instance needs >= 2 points");
+  ifgf_plan_s* P = new (std::nothrow) ifgf_plan_s();
+  if (!P) return fail(IFGF_ENOMEM, "out of host memory");
+  P->p_s = p_s;
+  P->p_ang = p_ang;
+  P->opts = o;
+  try {
+    std::vector<InstanceTree> trees(n_inst);
+    int threads = default_threads();
+    for (int i = 0; i < n_inst; ++i) {
+      std::string msg;
+      int rc = build_instance(points + 3 * offsets[i], offsets[i + 1] - offsets[i],
+                              kappas[i], leaf_size, o.levels, trees[i], msg);
+      if (rc != IFGF_OK) {
+        delete P;
+        return fail((ifgf_status)rc, n_inst > 1 ? "instance " + std::to_string(i) + ": " + msg : msg);
+      }
+      build_lists(trees[i], threads);
+    }
+    std::string msg;
+    int rc = merge_instances(trees, P->m, msg);
+    if (rc != IFGF_OK) {
+      delete P;
+      return fail((ifgf_status)rc, msg);
+    }
+    if (!o.host_only) {
+      if (o.device >= 0) HIP_TRY(hipSetDevice(o.device));
+      HIP_TRY(hipGetDevice(&P->device));
+      P->stream = (hipStream_t)o.stream;
+      build_device(P);
+    }
+  } catch (const std::bad_alloc&) {
+    delete P;
+    return fail(IFGF_ENOMEM, "out of host memory");
+  } catch (const HipError& e) {
+    delete P;
+    ifgf_status st = (e.e == hipErrorOutOfMemory) ? IFGF_ENOMEM : IFGF_EHIP;
+    return fail(st, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  }
+  fill_info(P);
+  P->info.plan_seconds =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  *out = P;
+  return IFGF_OK;
+}
+
+extern "C" {
+
+ifgf_status ifgf_default_opts(ifgf_opts* o) {
+  if (!o) return fail(IFGF_EINVAL, "null opts");
+  std::memset(o, 0, sizeof(*o));
+  o->precision = IFGF_FP64;
+  o->n_rhs = 1;
+  o->leaf_grid[0] = 2;
+  o->leaf_grid[1] = 4;
+  o->leaf_grid[2] = 8;
+  o->levels = 0;
+  o->stages = 3;
+  o->host_only = 0;
+  o->device = -1;
+  o->stream = nullptr;
+  return IFGF_OK;
+}
+
+ifgf_status ifgf_plan(ifgf_plan_t* plan, const double* points, int64_t n,
+                      double kappa, int p_s, int p_ang, double leaf_size) {
+  return ifgf_plan_ex(plan, points, n, kappa, p_s, p_ang, leaf_size, nullptr);
+}
+
+ifgf_status ifgf_plan_ex(ifgf_plan_t* plan, const double* points, int64_t n,
+                         double kappa, int p_s, int p_ang, double leaf_size,
+                         const ifgf_opts* opts) {
+  int64_t off[2] = {0, n};
+  return plan_common(plan, 1, off, points, &kappa, p_s, p_ang, leaf_size, opts);
+}
+
+ifgf_status ifgf_plan_batched(ifgf_plan_t* plan, int n_inst,
+                              const int64_t* offsets, const double* points,
+                              const double* kappas, int p_s, int p_ang,
+                              double leaf_size, const ifgf_opts* opts) {
+  return plan_common(plan, n_inst, offsets, points, kappas, p_s, p_ang,
+                     leaf_size, opts);
+}
+
+ifgf_status ifgf_apply(ifgf_plan_t P, const void* dens, void* out) {
+  if (!P || !dens || !out) return fail(IFGF_EINVAL, "null argument");
+  if (!P->device_ready) return fail(IFGF_EINVAL, "plan was built host-only");
+  hipError_t e = hipSetDevice(P->device);
+  Profiler prof;
+  Profiler* pp = nullptr;
+  if (e == hipSuccess && P->profiling) {
+    // Room for every launch of one apply.
+    size_t need = (size_t)P->prof_pending + 8 + 2 * (size_t)P->A.n_steps;
+    while (e == hipSuccess && P->prof_recs.size() < need) {
+      Profiler::Rec r{0, nullptr, nullptr};
+      e = hipEventCreate(&r.a);
+      if (e == hipSuccess) e = hipEventCreate(&r.b);
+      if (e == hipSuccess) P->prof_recs.push_back(r);
+    }
+    prof.recs = P->prof_recs.data();
+    prof.n = P->prof_pending;
+    prof.cap = (int)P->prof_recs.size();
+    pp = &prof;
+  }
+  if (e == hipSuccess)
+    e = launch_apply(P->A, P->p_s, P->p_ang, P->opts.precision, dens, out, P->stream, pp);
+  if (pp) P->prof_pending = prof.n;
+  if (e != hipSuccess)
+    return fail(IFGF_EHIP, std::string("apply: ") + hipGetErrorString(e));
+  return IFGF_OK;
+}
+
+ifgf_status ifgf_check(ifgf_plan_t P) {
+  if (!P) return fail(IFGF_EINVAL, "null plan");
+  if (!P->device_ready) return IFGF_OK;
+  int flag = 0, zero = 0;
+  hipError_t e = hipStreamSynchronize(P->stream);
+  if (e == hipSuccess) e = hipMemcpy(&flag, P->A.err, sizeof(int), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && flag) e = hipMemcpy(P->A.err, &zero, sizeof(int), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(IFGF_EHIP, std::string("check: ") + hipGetErrorString(e));
+  if (flag) return fail(IFGF_ELOOKUP, "a cone look-up missed during apply");
+  return IFGF_OK;
+}
+
+ifgf_status ifgf_profile(ifgf_plan_t P, int enable) {
+  if (!P) return fail(IFGF_EINVAL, "null plan");
+  P->profiling = enable != 0;
+  return IFGF_OK;
+}
+
+ifgf_status ifgf_profile_read(ifgf_plan_t P, ifgf_stage_times* t, int reset) {
+  if (!P || !t) return fail(IFGF_EINVAL, "null argument");
+  hipError_t e = hipSuccess;
+  if (P->prof_pending > 0) {
+    e = hipStreamSynchronize(P->stream);
+    for (int i = 0; e == hipSuccess && i < P->prof_pending; ++i) {
+      float ms = 0;
+      e = hipEventElapsedTime(&ms, P->prof_recs[i].a, P->prof_recs[i].b);
+      if (e == hipSuccess) {
+        P->prof_ms[P->prof_recs[i].stage] += ms;
+        P->prof_launches[P->prof_recs[i].stage] += 1;
+      }
+    }
+    P->prof_pending = 0;
+  }
+  if (e != hipSuccess) return fail(IFGF_EHIP, std::string("profile: ") + hipGetErrorString(e));
+  for (int k = 0; k < IFGF_N_STAGES; ++k) {
+    t->ms[k] = P->prof_ms[k];
+    t->launches[k] = P->prof_launches[k];
+    if (reset) {
+      P->prof_ms[k] = 0;
+      P->prof_launches[k] = 0;
+    }
+  }
+  return IFGF_OK;
+}
+
+ifgf_status ifgf_set_stream(ifgf_plan_t P, void* s) {
+  if (!P) return fail(IFGF_EINVAL, "null plan");
+  P->stream = (hipStream_t)s;
+  return IFGF_OK;
+}
+
+ifgf_status ifgf_plan_info(ifgf_plan_t P, ifgf_info* info) {
+  if (!P || !info) return fail(IFGF_EINVAL, "null argument");
+  *info = P->info;
+  return IFGF_OK;
+}
+
+ifgf_status ifgf_partition_counts(ifgf_plan_t P, int64_t* counts) {
+  if (!P || !counts) return fail(IFGF_EINVAL, "null argument");
+  partition_counts(P->m, counts);
+  return IFGF_OK;
+}
+
+void ifgf_destroy(ifgf_plan_t P) { delete P; }
+
+const char* ifgf_status_string(ifgf_status s) {
+  static thread_local std::string buf;
+  const char* base = "unknown status";
+  switch (s) {
+    case IFGF_OK: base = "ok"; break;
+    case IFGF_EINVAL: base = "invalid argument"; break;
+    case IFGF_ENOMEM: base = "out of memory"; break;
+    case IFGF_EDUPLICATE: base = "duplicate points"; break;
+    case IFGF_EHIP: base = "HIP error"; break;
+    case IFGF_EUNSUPPORTED: base = "unsupported"; break;
+    case IFGF_ELOOKUP: base = "cone look-up miss"; break;
+  }
+  buf = base;
+  if (s != IFGF_OK && !g_err.empty()) buf += ": " + g_err;
+  return buf.c_str();
+}
+
+}  // extern "C"

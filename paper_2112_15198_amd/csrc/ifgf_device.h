@@ -1,0 +1,114 @@
+// ifgf_device.h -- device-side views of a plan, shared by the kernels and
+// the host code that launches them.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ifgf {
+
+static constexpr unsigned long long kEmptyKey = ~0ull;
+static constexpr int kMaxRhs = 4;  // right-hand sides handled per apply
+
+// First-kind Chebyshev nodes t_j = cos((2j+1) pi / (2n)) on [-1, 1] and the
+// Lagrange product weights w_j = 1 / prod_{m != j} (t_j - t_m), radial (s)
+// and angular (a).
+struct ChebConst {
+  double ts[8], ws[8], ta[8], wa[8];
+};
+
+// One tree level, counted from the leaf (step l = D - d), all instances.
+struct StepDev {
+  int64_t nb;                 // relevant boxes
+  const double* center;       // 3 per box
+  const int* inst;            // instance of each box
+  const int* first;           // first point (sorted order)
+  const int* count;           // points per box
+  const int* child;           // 8 per box: children at step l-1, or -1
+  const int64_t* cous_begin;  // cousin CSR
+  const int* cous;
+  const int* pt_box;          // per point: its box at this step, or -1
+  const double* inst_h;       // per instance: h = (sqrt 3 / 2) H_d
+  // Cone grid (identical for every instance at a given step).
+  int ns, nt, np;
+  int64_t ngrid;              // ns * nt * np
+  double ds, dt, dp;          // cone widths in s, theta, phi
+  const double* s_node;       // ns * P_s node values of s
+  const double* t_node;       // nt * P_ang (sin, cos) of theta at the nodes
+  const double* p_node;       // np * P_ang (sin, cos) of phi at the nodes
+  // Relevant cone segments, sorted by key = box * ngrid + gamma (the order
+  // "box Morton order, then radial, elevation, azimuth").
+  int64_t ncones;
+  const unsigned long long* cone_key;
+  const unsigned long long* hkey;  // open-addressing table key -> slot
+  const int* hval;
+  unsigned long long hmask;
+};
+
+// Everything a kernel needs; passed by value (small), the per-step views
+// live in device memory.
+struct ApplyArgs {
+  int64_t n;                  // points, all instances
+  int nrhs;
+  int n_steps;
+  int stages;                 // bit 0 near field, bit 1 far field
+  const double* x;            // sorted coordinates
+  const double* y;
+  const double* z;
+  const int* perm;            // sorted index -> caller index
+  const double* inst_kappa;
+  const int64_t* nbr_begin;   // level-D neighbour CSR
+  const int* nbr;
+  const StepDev* step;        // device array of n_steps views
+  const StepDev* step_host;   // the same views in host memory (launch sizes)
+  ChebConst cheb;
+  int* err;                   // set when a cone look-up misses
+  void* dens_sorted;          // [N][nrhs] complex, sorted order
+  void* out_sorted;           // [N][nrhs] complex, sorted order
+  void* vbuf[2];              // cone values of two consecutive levels
+};
+
+struct MarkArgs {
+  unsigned long long* tab;
+  unsigned long long mask;
+  unsigned int* count;
+  int* overflow;
+  double margin;              // in cone widths
+};
+
+// Records a HIP event pair around each kernel launch of an apply.
+struct Profiler {
+  struct Rec {
+    int stage;
+    hipEvent_t a, b;
+  };
+  Rec* recs = nullptr;  // pool
+  int n = 0, cap = 0;
+  hipError_t begin(int stage, hipStream_t st) {
+    if (n >= cap) return hipErrorOutOfMemory;
+    recs[n].stage = stage;
+    return hipEventRecord(recs[n].a, st);
+  }
+  hipError_t end(hipStream_t st) { return hipEventRecord(recs[n++].b, st); }
+};
+
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n,
+                           unsigned long long v, hipStream_t st);
+hipError_t launch_mark(const ApplyArgs& A, int l, int ps, int pa,
+                       const MarkArgs& M, hipStream_t st);
+hipError_t launch_compact(const unsigned long long* tab, int64_t cap,
+                          unsigned long long* out, unsigned int* counter,
+                          hipStream_t st);
+hipError_t launch_build_lookup(const unsigned long long* keys, int64_t n,
+                               unsigned long long* tab, int* val,
+                               unsigned long long mask, int* overflow,
+                               hipStream_t st);
+hipError_t sort_keys(unsigned long long* keys, unsigned long long* tmp,
+                     int64_t n, int end_bit, void* scratch,
+                     size_t* scratch_bytes, hipStream_t st);
+hipError_t launch_apply(const ApplyArgs& A, int ps, int pa, int precision,
+                        const void* dens_user, void* out_user, hipStream_t st,
+                        Profiler* prof);
+
+}  // namespace ifgf

@@ -1,0 +1,812 @@
+// ifgf_kernels.hip -- gfx950 kernels of the IFGF evaluation.
+//
+// Numerical stages (paper, Section 2 and Algorithms "IFGF Method",
+// "Parallel LevelDEvaluations", "Parallel Propagation", "Parallel
+// Interpolation"):
+//   near_field_kernel    LevelDSingularInteractions: direct sum over the
+//                        level-D neighbour points, self excluded.
+//   leaf_eval_kernel     LevelDEvaluations: F_k^D (eq. fieldperbox) at the
+//                        interpolation nodes of every relevant leaf cone.
+//   interp_kernel        Interpolation(d): per target, sum over its cousin
+//                        boxes of I_P C(x) * G(x, x_k).
+//   prop_kernel          Propagation(d): per relevant parent cone node x,
+//                        sum over relevant children of I_P C_k(x) *
+//                        G(x,x_k)/G(x,x_j).
+// Plan-time kernels build the relevant cone segments
+// (eq. relevantconesegments) top-down, as open-addressing hash tables keyed
+// by (box, cone index) -- the GPU form of the per-box hash maps of
+// Section 3.2.2.
+//
+// Interpolants are stored as values at the tensor Chebyshev (first kind)
+// nodes and evaluated with Lagrange weights in product form; this is the same
+// polynomial as the coefficient form ("generate interpolant" becomes the
+// identity).  Every pass is target-owned: no atomics in the apply.
+//
+// Precision: T = double (FP64 mode) or float (FP32-mixed mode: values,
+// Lagrange weights and contractions in FP32; geometry, cone selection and
+// the phase argument kappa*r reduction in FP64).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <rocprim/device/device_radix_sort.hpp>
+
+#include "ifgf_device.h"
+
+namespace ifgf {
+
+#define IFGF_NO_CONTRACT _Pragma("clang fp contract(off)")
+
+static constexpr double kPiD = 3.14159265358979323846;
+static constexpr double kInv2Pi = 0.15915494309189533577;
+
+__device__ __forceinline__ int64_t gtid() {
+  return (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+}
+
+__device__ __forceinline__ unsigned long long hmix(unsigned long long x) {
+  x ^= x >> 30;
+  x *= 0xbf58476d1ce4e5b9ull;
+  x ^= x >> 27;
+  x *= 0x94d049bb133111ebull;
+  x ^= x >> 31;
+  return x;
+}
+
+// Slot of (box, gamma) in a level's relevant-cone table, or -1.
+__device__ __forceinline__ int cone_lookup(const StepDev& S,
+                                           unsigned long long key) {
+  unsigned long long h = hmix(key) & S.hmask;
+  for (unsigned long long probe = 0; probe <= S.hmask; ++probe) {
+    unsigned long long k = S.hkey[h];
+    if (k == key) return S.hval[h];
+    if (k == kEmptyKey) return -1;
+    h = (h + 1) & S.hmask;
+  }
+  return -1;
+}
+
+// Cone coordinates of y = x - x_k about a box centre (FP64, no FMA
+// contraction so that host and device round identically):
+// r = |y|, s = h/r, theta = atan2(|y_12|, y_3), phi = atan2(y_2, y_1) in
+// [0, 2 pi); q = (s/ds, theta/dt, phi/dp).
+struct ConeCoord {
+  double r;
+  double q[3];
+};
+
+__device__ __forceinline__ ConeCoord cone_coord(const StepDev& S, double h,
+                                                double y0, double y1,
+                                                double y2) {
+  IFGF_NO_CONTRACT
+  ConeCoord c;
+  double rho2 = y0 * y0 + y1 * y1;
+  c.r = sqrt(rho2 + y2 * y2);
+  double s = h / c.r;
+  double th = atan2(sqrt(rho2), y2);
+  double ph = atan2(y1, y0);
+  if (ph < 0) ph += 2.0 * kPiD;
+  c.q[0] = s / S.ds;
+  c.q[1] = th / S.dt;
+  c.q[2] = ph / S.dp;
+  return c;
+}
+
+__device__ __forceinline__ int cone_index(double q, int n, double& u) {
+  IFGF_NO_CONTRACT
+  double f = floor(q);
+  int i = (int)f;
+  if (f < 0) i = 0;
+  if (i > n - 1) i = n - 1;
+  u = 2.0 * (q - (double)i) - 1.0;
+  return i;
+}
+
+// Position of interpolation node (a, b, c) of cone (is, it, ip), relative to
+// the centre of its box: (h/s) (sin th cos ph, sin th sin ph, cos th).
+template <int PS, int PA>
+__device__ __forceinline__ void node_offset(const StepDev& S, double h,
+                                            int is, int it, int ip, int a,
+                                            int b, int c, double y[3]) {
+  IFGF_NO_CONTRACT
+  double s = S.s_node[is * PS + a];
+  double st = S.t_node[2 * (it * PA + b)];
+  double ct = S.t_node[2 * (it * PA + b) + 1];
+  double sp = S.p_node[2 * (ip * PA + c)];
+  double cp = S.p_node[2 * (ip * PA + c) + 1];
+  double r = h / s;
+  y[0] = r * st * cp;
+  y[1] = r * st * sp;
+  y[2] = r * ct;
+}
+
+// Lagrange basis at the N first-kind Chebyshev nodes t_m, product form:
+// L_j(u) = w_j prod_{m != j} (u - t_m), w_j = 1 / prod_{m != j} (t_j - t_m).
+template <int N, typename R>
+__device__ __forceinline__ void lagrange(R u, const double* t, const double* w,
+                                         R* L) {
+  R d[N];
+#pragma unroll
+  for (int m = 0; m < N; ++m) d[m] = u - (R)t[m];
+  R pre[N];
+  R acc = (R)1;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    pre[j] = acc;
+    acc *= d[j];
+  }
+  acc = (R)1;
+#pragma unroll
+  for (int j = N - 1; j >= 0; --j) {
+    L[j] = pre[j] * acc * (R)w[j];
+    acc *= d[j];
+  }
+}
+
+template <typename T> struct C2;
+template <> struct C2<double> { typedef double2 type; };
+template <> struct C2<float> { typedef float2 type; };
+
+// Tensor contraction sum_{a,b,c} Ls[a] Lt[b] Lp[c] v[(a PA + b) PA + c],
+// summed innermost-first (phi, then theta, then s).
+template <int PS, int PA, typename T>
+__device__ __forceinline__ void contract(const typename C2<T>::type* __restrict__ v,
+                                         const T* Ls, const T* Lt, const T* Lp,
+                                         T& re, T& im) {
+  T sr = 0, si = 0;
+#pragma unroll
+  for (int a = 0; a < PS; ++a) {
+    T tr = 0, ti = 0;
+#pragma unroll
+    for (int b = 0; b < PA; ++b) {
+      T pr = 0, pi = 0;
+#pragma unroll
+      for (int c = 0; c < PA; ++c) {
+        typename C2<T>::type x = v[(a * PA + b) * PA + c];
+        pr += Lp[c] * x.x;
+        pi += Lp[c] * x.y;
+      }
+      tr += Lt[b] * pr;
+      ti += Lt[b] * pi;
+    }
+    sr += Ls[a] * tr;
+    si += Ls[a] * ti;
+  }
+  re = sr;
+  im = si;
+}
+
+// e^{i phase} for phase = kappa * r given in FP64.  FP64 mode: FP64 sincos.
+// FP32-mixed: the number of turns kappa r / (2 pi) is reduced to [-1/2, 1/2]
+// in FP64, then sin/cos(pi * 2f) in FP32.
+template <typename T>
+__device__ __forceinline__ void expi(double phase, T& c, T& s);
+template <>
+__device__ __forceinline__ void expi<double>(double phase, double& c, double& s) {
+  sincos(phase, &s, &c);
+}
+template <>
+__device__ __forceinline__ void expi<float>(double phase, float& c, float& s) {
+  double t = phase * kInv2Pi;
+  float f = (float)(t - rint(t));
+  sincospif(2.0f * f, &s, &c);
+}
+
+// ---------------------------------------------------------------------------
+// Apply kernels.
+// ---------------------------------------------------------------------------
+
+// Densities, user layout [rhs][N] -> sorted layout [i][rhs].
+template <typename T>
+__global__ void perm_in_kernel(const typename C2<T>::type* __restrict__ in,
+                               typename C2<T>::type* __restrict__ out,
+                               const int* __restrict__ perm, int64_t n,
+                               int nrhs) {
+  int64_t t = gtid();
+  if (t >= n * nrhs) return;
+  int64_t i = t / nrhs;
+  int r = (int)(t - i * nrhs);
+  out[t] = in[(int64_t)r * n + perm[i]];
+}
+
+template <typename T>
+__global__ void perm_out_kernel(const typename C2<T>::type* __restrict__ in,
+                                typename C2<T>::type* __restrict__ out,
+                                const int* __restrict__ perm, int64_t n,
+                                int nrhs) {
+  int64_t t = gtid();
+  if (t >= n * nrhs) return;
+  int64_t i = t / nrhs;
+  int r = (int)(t - i * nrhs);
+  out[(int64_t)r * n + perm[i]] = in[t];
+}
+
+template <typename T>
+__global__ void zero_kernel(typename C2<T>::type* __restrict__ p, int64_t n) {
+  int64_t t = gtid();
+  if (t >= n) return;
+  typename C2<T>::type z;
+  z.x = 0;
+  z.y = 0;
+  p[t] = z;
+}
+
+// Near field: out[i] = sum over the points m of the level-D neighbour boxes
+// of box(i), m != i, of a_m e^{i kappa r}/(4 pi r).
+template <typename T, int MAXR>
+__global__ void __launch_bounds__(256)
+near_field_kernel(ApplyArgs A, typename C2<T>::type* __restrict__ out) {
+  int64_t i = gtid();
+  if (i >= A.n) return;
+  const StepDev& S = A.step[0];
+  int b = S.pt_box[i];
+  double kappa = A.inst_kappa[S.inst[b]];
+  double xi = A.x[i], yi = A.y[i], zi = A.z[i];
+  T accr[MAXR], acci[MAXR];
+#pragma unroll
+  for (int r = 0; r < MAXR; ++r) accr[r] = acci[r] = 0;
+  const T inv4pi = (T)(0.25 / kPiD);
+  for (int64_t j = A.nbr_begin[b]; j < A.nbr_begin[b + 1]; ++j) {
+    int nb = A.nbr[j];
+    int m0 = S.first[nb], m1 = m0 + S.count[nb];
+    for (int m = m0; m < m1; ++m) {
+      if (m == i) continue;
+      T dx = (T)(xi - A.x[m]), dy = (T)(yi - A.y[m]), dz = (T)(zi - A.z[m]);
+      T r = sqrt(dx * dx + dy * dy + dz * dz);
+      T c, s;
+      if constexpr (sizeof(T) == 8) {
+        sincos(kappa * (double)r, &s, &c);
+      } else {
+        sincosf((float)kappa * r, &s, &c);
+      }
+      T g = inv4pi / r;
+      c *= g;
+      s *= g;
+      const typename C2<T>::type* a = ((const typename C2<T>::type*)A.dens_sorted) + (int64_t)m * A.nrhs;
+      for (int r2 = 0; r2 < A.nrhs && r2 < MAXR; ++r2) {
+        typename C2<T>::type av = a[r2];
+        accr[r2] += av.x * c - av.y * s;
+        acci[r2] += av.x * s + av.y * c;
+      }
+    }
+  }
+  for (int r2 = 0; r2 < A.nrhs && r2 < MAXR; ++r2) {
+    typename C2<T>::type v;
+    v.x = accr[r2];
+    v.y = acci[r2];
+    out[i * A.nrhs + r2] = v;
+  }
+}
+
+// LevelDEvaluations: one thread per (relevant leaf cone, node p).
+// F_k(x_p) = sum_{x' in B_k} a(x') (|x_p - x_k|/|x_p - x'|)
+//            exp(i kappa (|x_p - x'| - |x_p - x_k|)).
+template <int PS, int PA, typename T, int MAXR>
+__global__ void __launch_bounds__(256)
+leaf_eval_kernel(ApplyArgs A, typename C2<T>::type* __restrict__ V) {
+  constexpr int P = PS * PA * PA;
+  const StepDev& S = A.step[0];
+  int64_t t = gtid();
+  if (t >= S.ncones * P) return;
+  int64_t slot = t / P;
+  int p = (int)(t - slot * P);
+  unsigned long long key = S.cone_key[slot];
+  int64_t b = (int64_t)(key / (unsigned long long)S.ngrid);
+  int64_t g = (int64_t)(key - (unsigned long long)b * S.ngrid);
+  int is = (int)(g / ((int64_t)S.nt * S.np));
+  int it = (int)((g / S.np) % S.nt);
+  int ip = (int)(g % S.np);
+  int a = p / (PA * PA), bb = (p / PA) % PA, cc = p % PA;
+  int inst = S.inst[b];
+  double h = S.inst_h[inst];
+  double kappa = A.inst_kappa[inst];
+  double cx = S.center[3 * b], cy = S.center[3 * b + 1], cz = S.center[3 * b + 2];
+  double y[3];
+  node_offset<PS, PA>(S, h, is, it, ip, a, bb, cc, y);
+  T accr[MAXR], acci[MAXR];
+#pragma unroll
+  for (int r = 0; r < MAXR; ++r) accr[r] = acci[r] = 0;
+  int m0 = S.first[b], m1 = m0 + S.count[b];
+  if constexpr (sizeof(T) == 8) {
+    IFGF_NO_CONTRACT
+    double x0 = cx + y[0], x1 = cy + y[1], x2 = cz + y[2];
+    double e0 = x0 - cx, e1 = x1 - cy, e2 = x2 - cz;
+    double rk = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+    for (int m = m0; m < m1; ++m) {
+      double dx = x0 - A.x[m], dy = x1 - A.y[m], dz = x2 - A.z[m];
+      double r = sqrt(dx * dx + dy * dy + dz * dz);
+      double s, c;
+      sincos(kappa * (r - rk), &s, &c);
+      double amp = rk / r;
+      c *= amp;
+      s *= amp;
+      const double2* av = ((const double2*)A.dens_sorted) + (int64_t)m * A.nrhs;
+      for (int r2 = 0; r2 < A.nrhs && r2 < MAXR; ++r2) {
+        double2 w = av[r2];
+        accr[r2] += w.x * c - w.y * s;
+        acci[r2] += w.x * s + w.y * c;
+      }
+    }
+  } else {
+    // Box-relative FP32: y node offset, q source offset; the phase
+    // |y - q| - |y| = (|q|^2 - 2 y.q) / (|y - q| + |y|) has no cancellation.
+    float y0 = (float)y[0], y1 = (float)y[1], y2 = (float)y[2];
+    float ry = sqrtf(y0 * y0 + y1 * y1 + y2 * y2);
+    float kf = (float)kappa;
+    for (int m = m0; m < m1; ++m) {
+      float q0 = (float)(A.x[m] - cx), q1 = (float)(A.y[m] - cy), q2 = (float)(A.z[m] - cz);
+      float d0 = y0 - q0, d1 = y1 - q1, d2 = y2 - q2;
+      float r = sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+      float diff = (q0 * q0 + q1 * q1 + q2 * q2 - 2.0f * (y0 * q0 + y1 * q1 + y2 * q2)) / (r + ry);
+      float s, c;
+      sincosf(kf * diff, &s, &c);
+      float amp = ry / r;
+      c *= amp;
+      s *= amp;
+      const float2* av = ((const float2*)A.dens_sorted) + (int64_t)m * A.nrhs;
+      for (int r2 = 0; r2 < A.nrhs && r2 < MAXR; ++r2) {
+        float2 w = av[r2];
+        accr[r2] += w.x * c - w.y * s;
+        acci[r2] += w.x * s + w.y * c;
+      }
+    }
+  }
+  for (int r2 = 0; r2 < A.nrhs && r2 < MAXR; ++r2) {
+    typename C2<T>::type v;
+    v.x = (T)accr[r2];
+    v.y = (T)acci[r2];
+    V[(slot * A.nrhs + r2) * P + p] = v;
+  }
+}
+
+// Interpolation(d) at step l: one thread per target point.
+template <int PS, int PA, typename T, int MAXR>
+__global__ void __launch_bounds__(256)
+interp_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V,
+              typename C2<T>::type* __restrict__ out) {
+  constexpr int P = PS * PA * PA;
+  int64_t i = gtid();
+  if (i >= A.n) return;
+  const StepDev& S = A.step[l];
+  int b = S.pt_box[i];
+  if (b < 0) return;
+  int inst = S.inst[b];
+  double h = S.inst_h[inst];
+  double kappa = A.inst_kappa[inst];
+  double xi = A.x[i], yi = A.y[i], zi = A.z[i];
+  T accr[MAXR], acci[MAXR];
+#pragma unroll
+  for (int r = 0; r < MAXR; ++r) accr[r] = acci[r] = 0;
+  for (int64_t j = S.cous_begin[b]; j < S.cous_begin[b + 1]; ++j) {
+    int k = S.cous[j];
+    double y0, y1, y2;
+    {
+      IFGF_NO_CONTRACT
+      y0 = xi - S.center[3 * k];
+      y1 = yi - S.center[3 * k + 1];
+      y2 = zi - S.center[3 * k + 2];
+    }
+    ConeCoord cc = cone_coord(S, h, y0, y1, y2);
+    double u0, u1, u2;
+    int is = cone_index(cc.q[0], S.ns, u0);
+    int it = cone_index(cc.q[1], S.nt, u1);
+    int ip = cone_index(cc.q[2], S.np, u2);
+    unsigned long long key = (unsigned long long)k * S.ngrid +
+                             ((unsigned long long)is * S.nt + it) * S.np + ip;
+    int slot = cone_lookup(S, key);
+    if (slot < 0) {
+      atomicOr(A.err, 1);
+      continue;
+    }
+    T Ls[PS], Lt[PA], Lp[PA];
+    lagrange<PS, T>((T)u0, A.cheb.ts, A.cheb.ws, Ls);
+    lagrange<PA, T>((T)u1, A.cheb.ta, A.cheb.wa, Lt);
+    lagrange<PA, T>((T)u2, A.cheb.ta, A.cheb.wa, Lp);
+    T gc, gs;
+    expi<T>(kappa * cc.r, gc, gs);
+    T amp = (T)(0.25 / (kPiD * cc.r));
+    gc *= amp;
+    gs *= amp;
+    const typename C2<T>::type* vb = V + (int64_t)slot * A.nrhs * P;
+    for (int r2 = 0; r2 < A.nrhs && r2 < MAXR; ++r2) {
+      T vr, vi;
+      contract<PS, PA, T>(vb + r2 * P, Ls, Lt, Lp, vr, vi);
+      accr[r2] += vr * gc - vi * gs;
+      acci[r2] += vr * gs + vi * gc;
+    }
+  }
+  for (int r2 = 0; r2 < A.nrhs && r2 < MAXR; ++r2) {
+    typename C2<T>::type v = out[i * A.nrhs + r2];
+    v.x += accr[r2];
+    v.y += acci[r2];
+    out[i * A.nrhs + r2] = v;
+  }
+}
+
+// Propagation from step l (level d) to step l+1 (level d-1): one thread per
+// (relevant parent cone, node p).
+template <int PS, int PA, typename T, int MAXR>
+__global__ void __launch_bounds__(256)
+prop_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc,
+            typename C2<T>::type* __restrict__ Vp) {
+  constexpr int P = PS * PA * PA;
+  const StepDev& S = A.step[l];
+  const StepDev& Q = A.step[l + 1];
+  int64_t t = gtid();
+  if (t >= Q.ncones * P) return;
+  int64_t slot = t / P;
+  int p = (int)(t - slot * P);
+  unsigned long long key = Q.cone_key[slot];
+  int64_t j = (int64_t)(key / (unsigned long long)Q.ngrid);
+  int64_t g = (int64_t)(key - (unsigned long long)j * Q.ngrid);
+  int is = (int)(g / ((int64_t)Q.nt * Q.np));
+  int it = (int)((g / Q.np) % Q.nt);
+  int ip = (int)(g % Q.np);
+  int a = p / (PA * PA), bb = (p / PA) % PA, cc = p % PA;
+  int inst = Q.inst[j];
+  double hp = Q.inst_h[inst];
+  double hc = S.inst_h[inst];
+  double kappa = A.inst_kappa[inst];
+  double cjx = Q.center[3 * j], cjy = Q.center[3 * j + 1], cjz = Q.center[3 * j + 2];
+  double yp[3];
+  node_offset<PS, PA>(Q, hp, is, it, ip, a, bb, cc, yp);
+  double x0, x1, x2, rj;
+  {
+    IFGF_NO_CONTRACT
+    x0 = cjx + yp[0];
+    x1 = cjy + yp[1];
+    x2 = cjz + yp[2];
+    double e0 = x0 - cjx, e1 = x1 - cjy, e2 = x2 - cjz;
+    rj = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+  }
+  T accr[MAXR], acci[MAXR];
+#pragma unroll
+  for (int r = 0; r < MAXR; ++r) accr[r] = acci[r] = 0;
+  for (int o = 0; o < 8; ++o) {
+    int k = Q.child[8 * j + o];
+    if (k < 0) continue;
+    double y0, y1, y2;
+    {
+      IFGF_NO_CONTRACT
+      y0 = x0 - S.center[3 * k];
+      y1 = x1 - S.center[3 * k + 1];
+      y2 = x2 - S.center[3 * k + 2];
+    }
+    ConeCoord c = cone_coord(S, hc, y0, y1, y2);
+    double u0, u1, u2;
+    int cs = cone_index(c.q[0], S.ns, u0);
+    int ct = cone_index(c.q[1], S.nt, u1);
+    int cp = cone_index(c.q[2], S.np, u2);
+    unsigned long long ckey = (unsigned long long)k * S.ngrid +
+                              ((unsigned long long)cs * S.nt + ct) * S.np + cp;
+    int cslot = cone_lookup(S, ckey);
+    if (cslot < 0) {
+      atomicOr(A.err, 1);
+      continue;
+    }
+    T Ls[PS], Lt[PA], Lp[PA];
+    lagrange<PS, T>((T)u0, A.cheb.ts, A.cheb.ws, Ls);
+    lagrange<PA, T>((T)u1, A.cheb.ta, A.cheb.wa, Lt);
+    lagrange<PA, T>((T)u2, A.cheb.ta, A.cheb.wa, Lp);
+    // G(x, x_k) / G(x, x_j) = (r_j / r_k) e^{i kappa (r_k - r_j)}.
+    T gc, gs;
+    expi<T>(kappa * (c.r - rj), gc, gs);
+    T amp = (T)(rj / c.r);
+    gc *= amp;
+    gs *= amp;
+    const typename C2<T>::type* vb = Vc + (int64_t)cslot * A.nrhs * P;
+    for (int r2 = 0; r2 < A.nrhs && r2 < MAXR; ++r2) {
+      T vr, vi;
+      contract<PS, PA, T>(vb + r2 * P, Ls, Lt, Lp, vr, vi);
+      accr[r2] += vr * gc - vi * gs;
+      acci[r2] += vr * gs + vi * gc;
+    }
+  }
+  for (int r2 = 0; r2 < A.nrhs && r2 < MAXR; ++r2) {
+    typename C2<T>::type v;
+    v.x = accr[r2];
+    v.y = acci[r2];
+    Vp[(slot * A.nrhs + r2) * P + p] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Plan-time kernels: relevant cone segments.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void hash_insert(unsigned long long* tab,
+                                            unsigned long long mask,
+                                            unsigned long long key,
+                                            unsigned int* count,
+                                            int* overflow) {
+  // Bounded probing: a (nearly) full table reports overflow and the planner
+  // retries with a larger one, so every insert terminates.
+  unsigned long long h = hmix(key) & mask;
+  for (unsigned long long probe = 0; probe <= mask && probe < 4096; ++probe) {
+    unsigned long long k = __atomic_load_n(&tab[h], __ATOMIC_RELAXED);
+    if (k == key) return;
+    if (k == kEmptyKey) {
+      unsigned long long prev = atomicCAS(&tab[h], kEmptyKey, key);
+      if (prev == kEmptyKey) {
+        atomicAdd(count, 1u);
+        return;
+      }
+      if (prev == key) return;
+    }
+    h = (h + 1) & mask;
+  }
+  atomicOr(overflow, 1);
+}
+
+// Insert the cone containing the point with coordinates q, plus the
+// adjacent cones when q lies within `margin` (in cone widths) of a cone
+// boundary, so that look-ups computed along a different FP64 path land in a
+// relevant cone.  phi is periodic.
+__device__ __forceinline__ void mark_cone(const StepDev& S, int64_t box,
+                                          const double q[3], MarkArgs M) {
+  int n[3] = {S.ns, S.nt, S.np};
+  int cand[3][3];
+  int nc[3];
+  for (int d = 0; d < 3; ++d) {
+    double u;
+    int i = cone_index(q[d], n[d], u);
+    double f = 0.5 * (u + 1.0);
+    nc[d] = 0;
+    cand[d][nc[d]++] = i;
+    if (f < M.margin) {
+      if (i > 0) cand[d][nc[d]++] = i - 1;
+      else if (d == 2 && n[d] > 1) cand[d][nc[d]++] = n[d] - 1;
+    }
+    if (f > 1.0 - M.margin) {
+      if (i < n[d] - 1) cand[d][nc[d]++] = i + 1;
+      else if (d == 2 && n[d] > 1) cand[d][nc[d]++] = 0;
+    }
+  }
+  for (int x = 0; x < nc[0]; ++x)
+    for (int y = 0; y < nc[1]; ++y)
+      for (int z = 0; z < nc[2]; ++z) {
+        unsigned long long key = (unsigned long long)box * S.ngrid +
+                                 ((unsigned long long)cand[0][x] * S.nt + cand[1][y]) * S.np +
+                                 cand[2][z];
+        hash_insert(M.tab, M.mask, key, M.count, M.overflow);
+      }
+}
+
+// Cones of the cousin boxes containing each point: thread per point x, loop
+// over the cousins B_k of its box at this step (M^d(x) = M B^d(x)).
+__global__ void mark_cousin_kernel(ApplyArgs A, int l, MarkArgs M) {
+  int64_t i = gtid();
+  if (i >= A.n) return;
+  const StepDev& S = A.step[l];
+  int b = S.pt_box[i];
+  if (b < 0) return;
+  double h = S.inst_h[S.inst[b]];
+  double xi = A.x[i], yi = A.y[i], zi = A.z[i];
+  for (int64_t j = S.cous_begin[b]; j < S.cous_begin[b + 1]; ++j) {
+    int k = S.cous[j];
+    double y0, y1, y2;
+    {
+      IFGF_NO_CONTRACT
+      y0 = xi - S.center[3 * k];
+      y1 = yi - S.center[3 * k + 1];
+      y2 = zi - S.center[3 * k + 2];
+    }
+    ConeCoord c = cone_coord(S, h, y0, y1, y2);
+    mark_cone(S, k, c.q, M);
+  }
+}
+
+// Cones of the children containing each node of a relevant parent cone.
+template <int PS, int PA>
+__global__ void mark_parent_kernel(ApplyArgs A, int l, MarkArgs M) {
+  constexpr int P = PS * PA * PA;
+  const StepDev& S = A.step[l];
+  const StepDev& Q = A.step[l + 1];
+  int64_t t = gtid();
+  if (t >= Q.ncones * P) return;
+  int64_t slot = t / P;
+  int p = (int)(t - slot * P);
+  unsigned long long key = Q.cone_key[slot];
+  int64_t j = (int64_t)(key / (unsigned long long)Q.ngrid);
+  int64_t g = (int64_t)(key - (unsigned long long)j * Q.ngrid);
+  int is = (int)(g / ((int64_t)Q.nt * Q.np));
+  int it = (int)((g / Q.np) % Q.nt);
+  int ip = (int)(g % Q.np);
+  int a = p / (PA * PA), bb = (p / PA) % PA, cc = p % PA;
+  int inst = Q.inst[j];
+  double hp = Q.inst_h[inst];
+  double hc = S.inst_h[inst];
+  double yp[3];
+  node_offset<PS, PA>(Q, hp, is, it, ip, a, bb, cc, yp);
+  double x0, x1, x2;
+  {
+    IFGF_NO_CONTRACT
+    x0 = Q.center[3 * j] + yp[0];
+    x1 = Q.center[3 * j + 1] + yp[1];
+    x2 = Q.center[3 * j + 2] + yp[2];
+  }
+  for (int o = 0; o < 8; ++o) {
+    int k = Q.child[8 * j + o];
+    if (k < 0) continue;
+    double y0, y1, y2;
+    {
+      IFGF_NO_CONTRACT
+      y0 = x0 - S.center[3 * k];
+      y1 = x1 - S.center[3 * k + 1];
+      y2 = x2 - S.center[3 * k + 2];
+    }
+    ConeCoord c = cone_coord(S, hc, y0, y1, y2);
+    mark_cone(S, k, c.q, M);
+  }
+}
+
+__global__ void fill_u64_kernel(unsigned long long* p, int64_t n,
+                                unsigned long long v) {
+  int64_t t = gtid();
+  if (t < n) p[t] = v;
+}
+
+__global__ void compact_keys_kernel(const unsigned long long* __restrict__ tab,
+                                    int64_t cap, unsigned long long* out,
+                                    unsigned int* counter) {
+  int64_t t = gtid();
+  if (t >= cap) return;
+  unsigned long long k = tab[t];
+  if (k != kEmptyKey) out[atomicAdd(counter, 1u)] = k;
+}
+
+// Final table: key -> slot (index in the sorted key array).
+__global__ void build_lookup_kernel(const unsigned long long* __restrict__ keys,
+                                    int64_t n, unsigned long long* tab,
+                                    int* val, unsigned long long mask,
+                                    int* overflow) {
+  int64_t t = gtid();
+  if (t >= n) return;
+  unsigned long long key = keys[t];
+  unsigned long long h = hmix(key) & mask;
+  for (unsigned long long probe = 0; probe <= mask; ++probe) {
+    unsigned long long prev = atomicCAS(&tab[h], kEmptyKey, key);
+    if (prev == kEmptyKey || prev == key) {
+      val[h] = (int)t;
+      return;
+    }
+    h = (h + 1) & mask;
+  }
+  atomicOr(overflow, 1);
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers.
+// ---------------------------------------------------------------------------
+
+static inline unsigned nblk(int64_t n, int bs) {
+  return (unsigned)((n + bs - 1) / bs);
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n,
+                           unsigned long long v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  fill_u64_kernel<<<nblk(n, 256), 256, 0, st>>>(p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_mark(const ApplyArgs& A, int l, int ps, int pa,
+                       const MarkArgs& M, hipStream_t st) {
+  if (A.n > 0) mark_cousin_kernel<<<nblk(A.n, 256), 256, 0, st>>>(A, l, M);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (l + 1 < A.n_steps && A.step_host[l + 1].ncones > 0) {
+    int64_t work = A.step_host[l + 1].ncones * (int64_t)(ps * pa * pa);
+#define IFGF_MARK(PS_, PA_)                                                   \
+  if (ps == PS_ && pa == PA_)                                                 \
+    mark_parent_kernel<PS_, PA_><<<nblk(work, 256), 256, 0, st>>>(A, l, M);
+    IFGF_MARK(3, 5) else IFGF_MARK(2, 3) else IFGF_MARK(5, 7) else return hipErrorInvalidValue;
+#undef IFGF_MARK
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+hipError_t launch_compact(const unsigned long long* tab, int64_t cap,
+                          unsigned long long* out, unsigned int* counter,
+                          hipStream_t st) {
+  compact_keys_kernel<<<nblk(cap, 256), 256, 0, st>>>(tab, cap, out, counter);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_lookup(const unsigned long long* keys, int64_t n,
+                               unsigned long long* tab, int* val,
+                               unsigned long long mask, int* overflow,
+                               hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  build_lookup_kernel<<<nblk(n, 256), 256, 0, st>>>(keys, n, tab, val, mask, overflow);
+  return hipGetLastError();
+}
+
+// Radix sort of 64-bit keys (rocPRIM).  With scratch == nullptr only the
+// scratch size is returned.
+hipError_t sort_keys(unsigned long long* keys, unsigned long long* tmp,
+                     int64_t n, int end_bit, void* scratch,
+                     size_t* scratch_bytes, hipStream_t st) {
+  hipError_t e = rocprim::radix_sort_keys(scratch, *scratch_bytes, keys, tmp,
+                                          (size_t)n, 0u, (unsigned)end_bit, st);
+  if (e != hipSuccess || scratch == nullptr) return e;
+  return hipMemcpyAsync(keys, tmp, sizeof(unsigned long long) * n,
+                        hipMemcpyDeviceToDevice, st);
+}
+
+// Launch with optional event timing of the launch.
+#define IFGF_TIMED(stage, launch)                                  \
+  do {                                                             \
+    if (prof) {                                                    \
+      hipError_t pe_ = prof->begin(stage, st);                     \
+      if (pe_ != hipSuccess) return pe_;                           \
+    }                                                              \
+    launch;                                                        \
+    if (prof) {                                                    \
+      hipError_t pe_ = prof->end(st);                              \
+      if (pe_ != hipSuccess) return pe_;                           \
+    }                                                              \
+  } while (0)
+
+template <int PS, int PA, typename T, int MAXR>
+static hipError_t apply_impl(const ApplyArgs& A, const void* dens_user,
+                             void* out_user, hipStream_t st, Profiler* prof) {
+  typedef typename C2<T>::type CT;
+  constexpr int P = PS * PA * PA;
+  const int64_t nr = A.n * A.nrhs;
+  CT* ds = (CT*)A.dens_sorted;
+  CT* os = (CT*)A.out_sorted;
+  IFGF_TIMED(0, (perm_in_kernel<T><<<nblk(nr, 256), 256, 0, st>>>(
+                    (const CT*)dens_user, ds, A.perm, A.n, A.nrhs)));
+  if (A.stages & 1)
+    IFGF_TIMED(1, (near_field_kernel<T, MAXR><<<nblk(A.n, 256), 256, 0, st>>>(A, os)));
+  else
+    IFGF_TIMED(1, (zero_kernel<T><<<nblk(nr, 256), 256, 0, st>>>(os, nr)));
+  if (A.stages & 2) {
+    CT* Vcur = (CT*)A.vbuf[0];
+    CT* Vnext = (CT*)A.vbuf[1];
+    const StepDev& S0 = A.step_host[0];
+    if (S0.ncones > 0)
+      IFGF_TIMED(2, (leaf_eval_kernel<PS, PA, T, MAXR>
+                     <<<nblk(S0.ncones * P, 256), 256, 0, st>>>(A, Vcur)));
+    for (int l = 0; l < A.n_steps; ++l) {
+      if (A.step_host[l].ncones > 0)
+        IFGF_TIMED(3, (interp_kernel<PS, PA, T, MAXR>
+                       <<<nblk(A.n, 256), 256, 0, st>>>(A, l, Vcur, os)));
+      if (l + 1 < A.n_steps && A.step_host[l + 1].ncones > 0) {
+        IFGF_TIMED(4, (prop_kernel<PS, PA, T, MAXR>
+                       <<<nblk(A.step_host[l + 1].ncones * P, 256), 256, 0, st>>>(
+                           A, l, Vcur, Vnext)));
+        CT* tmp = Vcur;
+        Vcur = Vnext;
+        Vnext = tmp;
+      }
+    }
+  }
+  IFGF_TIMED(5, (perm_out_kernel<T><<<nblk(nr, 256), 256, 0, st>>>(
+                    os, (CT*)out_user, A.perm, A.n, A.nrhs)));
+  return hipGetLastError();
+}
+
+hipError_t launch_apply(const ApplyArgs& A, int ps, int pa, int precision,
+                        const void* dens_user, void* out_user, hipStream_t st,
+                        Profiler* prof) {
+#define IFGF_APPLY(PS_, PA_)                                                  \
+  if (ps == PS_ && pa == PA_) {                                               \
+    if (precision == 0)                                                       \
+      return A.nrhs <= 1                                                      \
+                 ? apply_impl<PS_, PA_, double, 1>(A, dens_user, out_user, st, prof) \
+                 : apply_impl<PS_, PA_, double, kMaxRhs>(A, dens_user, out_user, st, prof); \
+    return A.nrhs <= 1                                                        \
+               ? apply_impl<PS_, PA_, float, 1>(A, dens_user, out_user, st, prof) \
+               : apply_impl<PS_, PA_, float, kMaxRhs>(A, dens_user, out_user, st, prof); \
+  }
+  IFGF_APPLY(3, 5)
+  IFGF_APPLY(2, 3)
+  IFGF_APPLY(5, 7)
+#undef IFGF_APPLY
+  return hipErrorInvalidValue;
+}
+
+}  // namespace ifgf

@@ -1,0 +1,194 @@
+"""GPU parity of libifgf.so against the CPU oracle.
+
+Bars (written in each test):
+  * FP64 mode vs the oracle's plain FP64 IFGF (same discrete choices):
+    relative l2 <= 1e-10 over all points.
+  * Both modes vs the FP64 direct sum of eq. (field1): relative l2 <= 1e-4.
+  * Near field alone: FP64 <= 1e-13, FP32-mixed <= 1e-6 (relative l2).
+All inputs are seeded; every case prints its name before touching the GPU.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2112_15198_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(b))
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(points, dens, kappa, precision="fp64", **kw):
+    """dens: (n_rhs, N) complex128 numpy -> (n_rhs, N) complex128 numpy."""
+    import torch
+    import paper_2112_15198_amd as ifgf
+    dens = np.atleast_2d(dens)
+    pl = ifgf.plan(points, kappa, precision=precision, n_rhs=dens.shape[0], **kw)
+    dt = torch.complex128 if precision == "fp64" else torch.complex64
+    a = torch.from_numpy(np.ascontiguousarray(dens)).to(dt).cuda()
+    out = pl.apply(a)
+    pl.check()
+    res = out.cpu().numpy().astype(np.complex128)
+    info = pl.info()
+    pl.close()
+    return res, info
+
+
+def test_fp64_matches_oracle_ifgf_sphere_5k():
+    w = W.make("sphere_5k")
+    say("fp64 sphere_5k N=5024")
+    g, info = run_gpu(w.points, w.dens, w.kappa)
+    o, oi = oracle.ifgf(w.points, w.dens[0], w.kappa, leaf_grid=(2, 4, 8), return_info=True)
+    assert info["D"] == oi["D"] == 5
+    # The GPU marks cones adjacent to a boundary within 1e-9 of a cone width
+    # as relevant too; it never has fewer relevant cones than the oracle.
+    assert all(gc >= oc for gc, oc in zip(info["cones"], oi["cones"][2:][::-1]))
+    assert relerr(g[0], o) <= 1e-10
+    ref = oracle.direct_sum(w.points, w.dens[0], w.kappa)
+    assert relerr(g[0], ref) <= 1e-4
+
+
+def test_fp32_mixed_sphere_5k_vs_direct_sum():
+    w = W.make("sphere_5k")
+    say("fp32 sphere_5k N=5024")
+    g, _ = run_gpu(w.points, w.dens, w.kappa, precision="fp32")
+    ref = oracle.direct_sum(w.points, w.dens[0], w.kappa)
+    assert relerr(g[0], ref) <= 1e-4
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32", 1e-6)])
+def test_near_field_alone(precision, tol):
+    n = 9001  # ragged: not a multiple of any block size
+    p = W.spheroid(n)
+    k = W.kappa_oblate_10ppw(n)
+    a = W.densities(n, 1, 31)
+    say("near field", precision, "N=", n)
+    g, _ = run_gpu(p, a, k, precision=precision, stages=1)
+    o = oracle.ifgf(p, a[0], k, far=False)
+    assert relerr(g[0], o) <= tol
+
+
+def test_far_field_alone_fp64():
+    n = 7333
+    p = W.fibonacci_sphere(n)
+    k = W.kappa_sphere_10ppw(n)
+    a = W.densities(n, 1, 32)
+    say("far field fp64 N=", n)
+    g, _ = run_gpu(p, a, k, stages=2)
+    o = oracle.ifgf(p, a[0], k, near=False, leaf_grid=(2, 4, 8))
+    assert relerr(g[0], o) <= 1e-10
+
+
+@pytest.mark.parametrize("geom", ["oblate", "clusters", "deep"])
+def test_fp64_matches_oracle_geometries(geom):
+    if geom == "oblate":
+        n = 12000
+        p, k, lv = W.spheroid(n), W.kappa_oblate_10ppw(n), 0
+    elif geom == "clusters":
+        rng = np.random.default_rng(3)
+        p = np.vstack([rng.normal(size=(1500, 3)) * 0.05 - [1.0, 0, 0],
+                       rng.normal(size=(1500, 3)) * 0.05 + [1.0, 0.3, 0]])
+        k, lv = 12.0, 0
+    else:  # forced deep tree on a small sphere: many propagation levels
+        p, k, lv = W.fibonacci_sphere(2500), 10.0, 6
+    a = W.densities(len(p), 1, 33)
+    say("fp64 geometry", geom, "N=", len(p))
+    g, _ = run_gpu(p, a, k, levels=lv)
+    o = oracle.ifgf(p, a[0], k, leaf_grid=(2, 4, 8), levels=lv)
+    assert relerr(g[0], o) <= 1e-10
+
+
+@pytest.mark.parametrize("ps,pa", [(2, 3), (5, 7)])
+def test_other_orders_match_oracle(ps, pa):
+    n = 3000
+    p = W.fibonacci_sphere(n)
+    k = W.kappa_sphere_10ppw(n)
+    a = W.densities(n, 1, 34)
+    say("fp64 order", ps, pa)
+    g, _ = run_gpu(p, a, k, p_s=ps, p_ang=pa, leaf_grid=(1, 2, 4))
+    o = oracle.ifgf(p, a[0], k, p_s=ps, p_ang=pa, leaf_grid=(1, 2, 4))
+    assert relerr(g[0], o) <= 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_multi_rhs_equals_single_rhs(precision):
+    n = 6000
+    p = W.spheroid(n)
+    k = W.kappa_oblate_10ppw(n)
+    a = W.densities(n, 4, 35)
+    say("multi-rhs", precision)
+    g4, _ = run_gpu(p, a, k, precision=precision)
+    tol = 1e-13 if precision == "fp64" else 1e-6
+    for r in range(4):
+        g1, _ = run_gpu(p, a[r:r + 1], k, precision=precision)
+        assert relerr(g4[r], g1[0]) <= tol
+
+
+def test_batched_equals_separate_plans():
+    import torch
+    import paper_2112_15198_amd as ifgf
+    pts = [W.fibonacci_sphere(3000), W.spheroid(5200), W.fibonacci_sphere(900)]
+    kap = [W.kappa_sphere_10ppw(3000), W.kappa_oblate_10ppw(5200), 9.0]
+    dens = [W.densities(len(q), 2, 40 + i) for i, q in enumerate(pts)]
+    say("batched 3 instances")
+    pl = ifgf.plan_batched(pts, kap, n_rhs=2)
+    a = torch.from_numpy(np.concatenate(dens, axis=1)).cuda()
+    out = pl.apply(a).cpu().numpy()
+    pl.check()
+    off = np.cumsum([0] + [len(q) for q in pts])
+    for i in range(3):
+        sep, _ = run_gpu(pts[i], dens[i], kap[i])
+        assert relerr(out[:, off[i]:off[i + 1]], sep) <= 1e-13
+        o = oracle.ifgf(pts[i], dens[i][1], kap[i], leaf_grid=(2, 4, 8))
+        assert relerr(out[1, off[i]:off[i + 1]], o) <= 1e-10
+
+
+def test_two_points_and_tiny():
+    p = np.array([[0.0, 0.0, 0.0], [0.3, 0.4, 0.0]])
+    a = np.array([[1.0 + 2.0j, -0.5 + 0.25j]])
+    say("two points")
+    g, _ = run_gpu(p, a, 2.0)
+    # A single cousin interaction at the closest cousin distance is the
+    # interpolation's worst case: compare with the oracle IFGF, and with the
+    # direct sum at a looser bound.
+    o = oracle.ifgf(p, a[0], 2.0, leaf_grid=(2, 4, 8))
+    assert relerr(g[0], o) <= 1e-10
+    ref = oracle.direct_sum(p, a[0], 2.0)
+    assert relerr(g[0], ref) <= 1e-3
+    # Near field only reproduces the pair exactly.
+    g, _ = run_gpu(p, a, 2.0, stages=1)
+    nf = oracle.ifgf(p, a[0], 2.0, far=False)
+    np.testing.assert_allclose(g[0], nf, rtol=1e-14, atol=0)
+
+
+def test_linearity_fp64():
+    n = 4000
+    p = W.fibonacci_sphere(n)
+    k = W.kappa_sphere_10ppw(n)
+    a, b = W.densities(n, 2, 36)
+    al, be = 0.7 - 1.2j, 2.0 + 0.1j
+    say("linearity")
+    g, _ = run_gpu(p, np.stack([a, b, al * a + be * b]), k)
+    assert relerr(g[2], al * g[0] + be * g[1]) <= 1e-13
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_sphere_321k_sampled_vs_direct_sum(precision):
+    w = W.make("sphere_321k")
+    say("sphere_321k", precision)
+    g, info = run_gpu(w.points, w.dens, w.kappa, precision=precision)
+    assert info["D"] == 8
+    ref = oracle.direct_sum(w.points, w.dens[0], w.kappa, w.targets)
+    err = relerr(g[0][w.targets], ref)
+    print(f"sphere_321k {precision} rel-err {err:.3e}", flush=True)
+    assert err <= 1e-4
