@@ -67,6 +67,19 @@ typedef struct ifgf_opts {
                        called on such a plan */
   int device;       /* HIP device ordinal; -1 uses the current device */
   void* stream;     /* hipStream_t used by ifgf_apply; NULL = null stream */
+  int prop_kernel;  /* propagation kernel per level: 0 chooses by the number
+                       of boxes sharing each parent cone index (grouped
+                       matrix-core form when >= 32 on average, per-node form
+                       otherwise), 1 forces the per-node form, 2 the grouped
+                       form */
+  int lookup;       /* cone look-up: 0 dense tables where a level's table
+                       (boxes x cone grid) has <= 2^28 entries, hash tables
+                       elsewhere; 1 hash tables everywhere */
+  double cone_margin; /* a point within cone_margin cone widths of a cone
+                       boundary also marks the adjacent cone relevant, so
+                       that look-ups along other rounding paths never miss;
+                       default 1e-9; 0 gives exactly the point-based
+                       relevant cones of eq. (relevantconesegments) */
 } ifgf_opts;
 
 /* Size information about a plan (ifgf_plan_info). */
@@ -163,6 +176,13 @@ ifgf_status ifgf_profile_read(ifgf_plan_t plan, ifgf_stage_times* times,
 
 /* Sizes and counts of the plan. */
 ifgf_status ifgf_plan_info(ifgf_plan_t plan, ifgf_info* info);
+
+/* Relevant cone segments of step l (level D - l): writes min(capacity,
+ * info.cones[l]) keys box * grid[l] + gamma to the host array keys, in
+ * ascending order (boxes in Morton order, the batched instances
+ * concatenated; gamma = (i_s n_theta + i_theta) n_phi + i_phi). */
+ifgf_status ifgf_cone_keys(ifgf_plan_t plan, int step, uint64_t* keys,
+                           int64_t capacity);
 
 /* Per point (caller order): the number of sources covered by the near-field
  * neighbour boxes (itself included) plus the points of every cousin box of

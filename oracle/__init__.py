@@ -35,6 +35,8 @@ def _load():
         lib.oracle_partition_counts.argtypes = [P, c_i64, c_dbl, c_dbl, c_int, P]
         lib.oracle_interp_nodes.argtypes = [c_int, c_int, P, P]
         lib.oracle_interp_eval.argtypes = [c_int, c_int, P, P, c_i64, P]
+        lib.oracle_cone_keys.argtypes = [P, c_i64, c_dbl, c_dbl, P, c_int, P, c_i64]
+        lib.oracle_cone_keys.restype = c_i64
         for f in (lib.oracle_direct_sum, lib.oracle_ifgf,
                   lib.oracle_partition_counts, lib.oracle_interp_nodes,
                   lib.oracle_interp_eval):
@@ -127,3 +129,21 @@ def interp_eval(p_s, p_ang, values, u):
     _load().oracle_interp_eval(p_s, p_ang, _ptr(v.view(np.float64)), _ptr(uu),
                                uu.shape[0], _ptr(out))
     return out.view(np.complex128)
+
+
+def cone_keys(points, kappa, level, p_s=3, p_ang=5, leaf_size=0.25,
+              leaf_grid=(1, 2, 4), levels=0):
+    """Sorted relevant-cone keys box * grid + gamma of octree level `level`."""
+    p = _pts(points)
+    n = p.shape[0]
+    opts = np.array([p_s, p_ang, leaf_grid[0], leaf_grid[1], leaf_grid[2],
+                     levels, 0, 0], dtype=np.int32)
+    L = _load()
+    cnt = L.oracle_cone_keys(_ptr(p), n, float(kappa), float(leaf_size),
+                             _ptr(opts), int(level), None, 0)
+    if cnt < 0:
+        raise RuntimeError("oracle_cone_keys failed")
+    out = np.zeros(cnt, dtype=np.uint64)
+    L.oracle_cone_keys(_ptr(p), n, float(kappa), float(leaf_size), _ptr(opts),
+                       int(level), _ptr(out), cnt)
+    return out

@@ -715,3 +715,33 @@ extern "C" int oracle_interp_eval(int p_s, int p_ang, const double* values,
   }
   return 0;
 }
+
+// Relevant cone segments of level d as sorted keys box * (n_s n_theta n_phi)
+// + gamma (boxes numbered in Morton order).  Returns the number of keys
+// (writing at most cap of them), or -1 on invalid input.
+extern "C" int64_t oracle_cone_keys(const double* pts, int64_t n, double kappa,
+                                    double leaf_size, const int* opts, int d,
+                                    uint64_t* out, int64_t cap) {
+  if (n < 2 || !(kappa > 0) || !(leaf_size > 0)) return -1;
+  Oracle O;
+  O.n = n;
+  O.x_user = pts;
+  std::vector<double> zero(2 * n, 0.0);
+  O.a_user = zero.data();
+  O.kappa = kappa;
+  O.o = Options{opts[0], opts[1], opts[2], opts[3], opts[4], opts[5], 0, 0};
+  O.P = O.o.p_s * O.o.p_ang * O.o.p_ang;
+  O.t_s.resize(O.o.p_s);
+  O.t_a.resize(O.o.p_ang);
+  for (int j = 0; j < O.o.p_s; ++j) O.t_s[j] = std::cos((2.0 * j + 1.0) * PI / (2.0 * O.o.p_s));
+  for (int j = 0; j < O.o.p_ang; ++j) O.t_a[j] = std::cos((2.0 * j + 1.0) * PI / (2.0 * O.o.p_ang));
+  O.build_tree(leaf_size);
+  if (d < 3 || d > O.D) return -1;
+  O.build_cones();
+  const Level& L = O.lev[d];
+  uint64_t grid = (uint64_t)L.ns * L.nt * L.np;
+  int64_t cnt = (int64_t)L.cones.size();
+  for (int64_t i = 0; i < cnt && i < cap; ++i)
+    out[i] = (uint64_t)L.cones[i].first * grid + (uint64_t)L.cones[i].second;
+  return cnt;
+}

@@ -111,6 +111,10 @@ static ifgf_status validate(int p_s, int p_ang, const ifgf_opts& o) {
       return fail(IFGF_EINVAL, "leaf_grid entries must be in [1, 4096]");
   if (o.levels != 0 && o.levels < 3) return fail(IFGF_EINVAL, "levels must be 0 or >= 3");
   if (o.stages < 0 || o.stages > 3) return fail(IFGF_EINVAL, "stages must be in [0, 3]");
+  if (o.prop_kernel < 0 || o.prop_kernel > 2) return fail(IFGF_EINVAL, "prop_kernel must be 0, 1 or 2");
+  if (o.lookup < 0 || o.lookup > 1) return fail(IFGF_EINVAL, "lookup must be 0 or 1");
+  if (!(o.cone_margin >= 0.0 && o.cone_margin < 0.25))
+    return fail(IFGF_EINVAL, "cone_margin must be in [0, 0.25)");
   bool ok = (p_s == 3 && p_ang == 5) || (p_s == 2 && p_ang == 3) || (p_s == 5 && p_ang == 7);
   if (!ok && !o.host_only)
     return fail(IFGF_EUNSUPPORTED, "no kernel compiled for this (p_s, p_ang)");
@@ -178,6 +182,7 @@ static void build_device(ifgf_plan_s* P) {
     D.cous = P->upload(S.cous);
     D.pt_box = P->upload(S.pt_box);
     D.inst_h = P->upload(S.inst_h);
+    D.inst_H = P->upload(S.inst_H);
     // Cone grid: leaf grid doubled per dimension for every level up.
     D.ns = P->opts.leaf_grid[0] << l;
     D.nt = P->opts.leaf_grid[1] << l;
@@ -236,7 +241,7 @@ static void build_device(ifgf_plan_s* P) {
       HIP_TRY(launch_fill_u64(tab, (int64_t)cap, kEmptyKey, st));
       HIP_TRY(hipMemsetAsync(counters, 0, 2 * sizeof(unsigned int), st));
       HIP_TRY(hipMemsetAsync(overflow, 0, sizeof(int), st));
-      MarkArgs M{tab, (unsigned long long)(cap - 1), counters, overflow, 1e-9};
+      MarkArgs M{tab, (unsigned long long)(cap - 1), counters, overflow, P->opts.cone_margin};
       HIP_TRY(launch_mark(A, l, ps, pa, M, st));
       int ovf = 0;
       HIP_TRY(hipMemcpyAsync(&count, counters, sizeof(unsigned int), hipMemcpyDeviceToHost, st));
@@ -273,13 +278,59 @@ static void build_device(ifgf_plan_s* P) {
     HIP_TRY(hipMemcpyAsync(&ovf, overflow, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (ovf) throw HipError{hipErrorUnknown, "cone lookup table overflow"};
-    // Work counts of this step (for throughput and roofline figures).
+    // Dense look-up table where it is small enough.
+    D.table = nullptr;
+    if (P->opts.lookup == 0 && (double)D.nb * (double)D.ngrid <= (double)(int64_t(1) << 28)) {
+      int* tbl = P->dalloc<int>(D.nb * D.ngrid);
+      HIP_TRY(launch_fill_i32(tbl, D.nb * D.ngrid, -1, st));
+      HIP_TRY(launch_scatter_table(keys, count, tbl, st));
+      D.table = tbl;
+    }
+    // Work counts of this step (for throughput and roofline figures), and
+    // the grouping of its cones by (instance, gamma) for propagation.
     {
       std::vector<unsigned long long> hkeys(count);
       if (count > 0)
         HIP_TRY(hipMemcpy(hkeys.data(), keys, sizeof(unsigned long long) * count,
                           hipMemcpyDeviceToHost));
       const MergedStep& S = m.step[l];
+      D.prop_grouped = 0;
+      D.nchunks = 0;
+      if (l >= 1 && count > 0) {
+        const uint64_t ng = (uint64_t)D.ngrid;
+        std::vector<int32_t> order(count);
+        for (int64_t i = 0; i < (int64_t)count; ++i) order[i] = (int32_t)i;
+        auto gk = [&](int32_t i) {
+          uint64_t b = hkeys[i] / ng;
+          return std::make_pair(S.inst[b], hkeys[i] - b * ng);
+        };
+        std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+          auto a = gk(x), b = gk(y);
+          return a != b ? a < b : x < y;
+        });
+        const int cbox = chunk_boxes(P->opts.precision, P->opts.n_rhs);
+        std::vector<int64_t> cstart;
+        std::vector<int32_t> clen;
+        int64_t groups = 0;
+        for (int64_t i = 0; i < (int64_t)count; ++i) {
+          bool same = i > 0 && gk(order[i]) == gk(order[i - 1]);
+          if (!same) ++groups;
+          if (!same || clen.back() == cbox) {
+            cstart.push_back(i);
+            clen.push_back(0);
+          }
+          clen.back() += 1;
+        }
+        double mean = (double)count / (double)std::max<int64_t>(groups, 1);
+        int mode = P->opts.prop_kernel;
+        D.prop_grouped = PP <= kMfmaMaxP && (mode == 2 || (mode == 0 && mean >= 32.0));
+        if (D.prop_grouped) {
+          D.gslot = P->upload(order);
+          D.chunk_start = P->upload(cstart);
+          D.chunk_len = P->upload(clen);
+          D.nchunks = (int64_t)cstart.size();
+        }
+      }
       int64_t pairs_l = 0;
       for (unsigned long long k : hkeys) {
         int64_t b = (int64_t)(k / (unsigned long long)D.ngrid);
@@ -421,6 +472,7 @@ ifgf_status ifgf_default_opts(ifgf_opts* o) {
   o->host_only = 0;
   o->device = -1;
   o->stream = nullptr;
+  o->cone_margin = 1e-9;
   return IFGF_OK;
 }
 
@@ -526,6 +578,19 @@ ifgf_status ifgf_set_stream(ifgf_plan_t P, void* s) {
 ifgf_status ifgf_plan_info(ifgf_plan_t P, ifgf_info* info) {
   if (!P || !info) return fail(IFGF_EINVAL, "null argument");
   *info = P->info;
+  return IFGF_OK;
+}
+
+ifgf_status ifgf_cone_keys(ifgf_plan_t P, int step, uint64_t* keys, int64_t capacity) {
+  if (!P || (!keys && capacity > 0)) return fail(IFGF_EINVAL, "null argument");
+  if (!P->device_ready) return fail(IFGF_EINVAL, "plan was built host-only");
+  if (step < 0 || step >= P->A.n_steps) return fail(IFGF_EINVAL, "step out of range");
+  int64_t n = std::min<int64_t>(capacity, P->steps_h[step].ncones);
+  if (n <= 0) return IFGF_OK;
+  hipError_t e = hipSetDevice(P->device);
+  if (e == hipSuccess)
+    e = hipMemcpy(keys, P->steps_h[step].cone_key, sizeof(uint64_t) * n, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(IFGF_EHIP, std::string("cone keys: ") + hipGetErrorString(e));
   return IFGF_OK;
 }
 

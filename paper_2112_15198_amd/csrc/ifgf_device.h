@@ -30,6 +30,7 @@ struct StepDev {
   const int* cous;
   const int* pt_box;          // per point: its box at this step, or -1
   const double* inst_h;       // per instance: h = (sqrt 3 / 2) H_d
+  const double* inst_H;       // per instance: box side H_d
   // Cone grid (identical for every instance at a given step).
   int ns, nt, np;
   int64_t ngrid;              // ns * nt * np
@@ -44,7 +45,24 @@ struct StepDev {
   const unsigned long long* hkey;  // open-addressing table key -> slot
   const int* hval;
   unsigned long long hmask;
+  const int* table;           // dense key -> slot table (nb * ngrid), or null
+  // Propagation into this step, grouped: the relevant cones sorted by
+  // (instance, gamma, box) and cut into chunks of boxes sharing one gamma,
+  // whose node geometry is computed once per chunk.
+  int prop_grouped;           // 1: use the grouped propagation kernel
+  int64_t nchunks;
+  const int* gslot;           // slots in (instance, gamma, box) order
+  const int64_t* chunk_start; // first index into gslot of each chunk
+  const int* chunk_len;       // boxes in each chunk (<= chunk_boxes())
 };
+
+// Largest P = P_s P_ang^2 with a matrix-core propagation kernel.
+static constexpr int kMfmaMaxP = 125;
+
+// Boxes per chunk of the grouped (matrix-core) propagation: kSubChunks
+// sub-chunks of 32 (FP32) or 16 (FP64) GEMM columns.
+static constexpr int kSubChunks = 8;
+int chunk_boxes(int precision, int nrhs);
 
 // Everything a kernel needs; passed by value (small), the per-step views
 // live in device memory.
@@ -97,6 +115,9 @@ hipError_t launch_fill_u64(unsigned long long* p, int64_t n,
                            unsigned long long v, hipStream_t st);
 hipError_t launch_mark(const ApplyArgs& A, int l, int ps, int pa,
                        const MarkArgs& M, hipStream_t st);
+hipError_t launch_fill_i32(int* p, int64_t n, int v, hipStream_t st);
+hipError_t launch_scatter_table(const unsigned long long* keys, int64_t n,
+                                int* table, hipStream_t st);
 hipError_t launch_compact(const unsigned long long* tab, int64_t cap,
                           unsigned long long* out, unsigned int* counter,
                           hipStream_t st);

@@ -56,6 +56,7 @@ __device__ __forceinline__ unsigned long long hmix(unsigned long long x) {
 // Slot of (box, gamma) in a level's relevant-cone table, or -1.
 __device__ __forceinline__ int cone_lookup(const StepDev& S,
                                            unsigned long long key) {
+  if (S.table) return S.table[key];
   unsigned long long h = hmix(key) & S.hmask;
   for (unsigned long long probe = 0; probe <= S.hmask; ++probe) {
     unsigned long long k = S.hkey[h];
@@ -510,6 +511,313 @@ prop_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc,
   }
 }
 
+// Matrix-core (MFMA 16x16x4) operand layouts on gfx950, one wave:
+//   A (16 x 4):  lane l holds A[l % 16][l / 16]
+//   B (4 x 16):  lane l holds B[l / 16][l % 16]
+//   D (16 x 16): lane l holds D[row(l, r)][l % 16], r = 0..3, with
+//                row = 4 (l / 16) + r for FP32 and 4 r + l / 16 for FP64.
+template <typename T> struct Mfma;
+template <> struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+template <> struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+
+// Boxes per chunk of the grouped propagation (columns of the GEMM are
+// (box, right-hand side) pairs; 32 FP32 or 16 FP64 columns per chunk).
+static constexpr int kMfmaThreads = 256;
+
+template <typename T, int MAXR>
+struct ChunkCols {
+  static constexpr int boxes = (sizeof(T) == 4 ? 32 : 16) / MAXR;
+};
+
+// Propagation as batched small GEMMs on the matrix cores.  One block (4
+// waves) per chunk of parent cones sharing (instance, gamma'), processed
+// in sub-chunks of CB boxes.  The node geometry -- the child cone alpha,
+// the local coordinates u and the ratio G(x,x_k)/G(x,x_j) of node p of
+// gamma' seen from the child in octant o -- does not depend on the box and
+// is computed once per block.  For every octant o and child cone alpha,
+// the nodes p with alpha(p) = alpha are the rows of
+//     C[p][(box, rhs)] = sum_q W[p][q] X[q][(box, rhs)],
+//     W[p][q] = L_a(u_s(p)) L_b(u_theta(p)) L_c(u_phi(p)),  q = (a, b, c),
+// X holding the child cone values of the boxes' children in octant o; the
+// product runs on 16x16x4 MFMA tiles and ratio(p) * C accumulates per
+// (box, p) in LDS.  The block owns its parent cones: no atomics.
+template <int PS, int PA, typename T, int MAXR>
+__global__ void __launch_bounds__(kMfmaThreads)
+prop_mfma_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc,
+                 typename C2<T>::type* __restrict__ Vp) {
+  typedef typename C2<T>::type CT;
+  typedef typename Mfma<T>::v4 V4;
+  constexpr int P = PS * PA * PA;
+  static_assert(P <= 128, "two nodes per lane");
+  constexpr int NW = PS + 2 * PA;
+  constexpr int KP = (P + 3) / 4 * 4;
+  constexpr int CB = ChunkCols<T, MAXR>::boxes;
+  constexpr int NCOL = CB * MAXR;  // <= 32 columns
+  constexpr int NAMAX = 8;         // child cones per octant with a cached slot
+  constexpr int NWP = NW + 1;      // weights per node plus a zero slot
+  __shared__ T s_L[8 * P * NWP];          // Lagrange weights of (o, p), then 0
+  __shared__ T s_rat[8 * P * 2];
+  __shared__ int s_alpha[8 * P];          // child cone alpha of (o, p)
+  __shared__ int s_dist[8 * P];           // distinct child cones per octant
+  __shared__ unsigned char s_rows[8 * P]; // nodes of octant o grouped by alpha
+  __shared__ int s_rbeg[8 * (P + 1)];
+  __shared__ int s_na[8];
+  __shared__ T s_y[NCOL * P * 2];
+  __shared__ int s_pslot[CB], s_box[CB];
+  __shared__ int s_nlist[8 * CB], s_child[8 * CB], s_no[8], s_ipre[9];
+  __shared__ int s_cslot[8 * CB * NAMAX];
+  // For q = (a, b, c): the offsets of L_a, L_b, L_c in a node's weights,
+  // packed a | (PS + b) << 8 | (PS + PA + c) << 16; zero weight past P.
+  __shared__ unsigned int s_qidx[KP];
+
+  const StepDev& S = A.step[l];
+  const StepDev& Q = A.step[l + 1];
+  constexpr int NWAVES = kMfmaThreads / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nrhs = A.nrhs;
+  const int64_t c = blockIdx.x;
+  const int64_t g0 = Q.chunk_start[c];
+  const int nchunk = Q.chunk_len[c];
+  const unsigned long long key0 = Q.cone_key[Q.gslot[g0]];
+  const int64_t j0 = (int64_t)(key0 / (unsigned long long)Q.ngrid);
+  const int64_t g = (int64_t)(key0 - (unsigned long long)j0 * Q.ngrid);
+  const int is = (int)(g / ((int64_t)Q.nt * Q.np));
+  const int it = (int)((g / Q.np) % Q.nt);
+  const int ip = (int)(g % Q.np);
+  const int inst = Q.inst[j0];
+  const double hp = Q.inst_h[inst];
+  const double hc = S.inst_h[inst];
+  const double Hc = S.inst_H[inst];
+  const double kappa = A.inst_kappa[inst];
+
+  for (int q = tid; q < KP; q += blockDim.x)
+    s_qidx[q] = q < P ? (unsigned)(q / (PA * PA)) | ((unsigned)(PS + (q / PA) % PA) << 8) |
+                            ((unsigned)(PS + PA + q % PA) << 16)
+                      : (unsigned)NW | ((unsigned)NW << 8) | ((unsigned)NW << 16);
+  // Node geometry, once per block.
+  for (int i = tid; i < 8 * P; i += blockDim.x) {
+    const int o = i / P, p = i - (i / P) * P;
+    const int a = p / (PA * PA), bb = (p / PA) % PA, cc = p % PA;
+    double yp[3];
+    node_offset<PS, PA>(Q, hp, is, it, ip, a, bb, cc, yp);
+    double y0, y1, y2, rj;
+    {
+      IFGF_NO_CONTRACT
+      // Child centre minus parent centre: (bit - 1/2) H_child per axis.
+      y0 = yp[0] - (((o >> 2) & 1) ? 0.5 * Hc : -0.5 * Hc);
+      y1 = yp[1] - (((o >> 1) & 1) ? 0.5 * Hc : -0.5 * Hc);
+      y2 = yp[2] - ((o & 1) ? 0.5 * Hc : -0.5 * Hc);
+      rj = sqrt(yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]);
+    }
+    ConeCoord cr = cone_coord(S, hc, y0, y1, y2);
+    double u0, u1, u2;
+    int cs = cone_index(cr.q[0], S.ns, u0);
+    int ct = cone_index(cr.q[1], S.nt, u1);
+    int cp = cone_index(cr.q[2], S.np, u2);
+    s_alpha[i] = (cs * S.nt + ct) * S.np + cp;
+    T* L = s_L + i * NWP;
+    lagrange<PS, T>((T)u0, A.cheb.ts, A.cheb.ws, L);
+    lagrange<PA, T>((T)u1, A.cheb.ta, A.cheb.wa, L + PS);
+    lagrange<PA, T>((T)u2, A.cheb.ta, A.cheb.wa, L + PS + PA);
+    L[NW] = 0;
+    T gc, gs;
+    expi<T>(kappa * (cr.r - rj), gc, gs);
+    T amp = (T)(rj / cr.r);
+    s_rat[2 * i] = gc * amp;
+    s_rat[2 * i + 1] = gs * amp;
+  }
+  __syncthreads();
+  // Per octant (wave w: octants w and w + 4), the distinct child cones and
+  // the nodes grouped by child cone, with wave ballots; lane holds nodes
+  // lane and lane + 64.
+  for (int o = wave; o < 8; o += NWAVES) {
+    const bool has0 = lane < P, has1 = lane + 64 < P;
+    const int a0 = has0 ? s_alpha[o * P + lane] : -1;
+    const int a1 = has1 ? s_alpha[o * P + lane + 64] : -1;
+    bool f0 = has0, f1 = has1;
+    int k0 = 0, k1 = 0, na = 0;
+    for (;;) {
+      const unsigned long long m0 = __ballot(f0), m1 = __ballot(f1);
+      if (m0 == 0ull && m1 == 0ull) break;
+      const int lead = m0 ? __shfl(a0, __ffsll((long long)m0) - 1)
+                          : __shfl(a1, __ffsll((long long)m1) - 1);
+      if (f0 && a0 == lead) { k0 = na; f0 = false; }
+      if (f1 && a1 == lead) { k1 = na; f1 = false; }
+      if (lane == 0) s_dist[o * P + na] = lead;
+      ++na;
+    }
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    int base = 0;
+    for (int k = 0; k < na; ++k) {
+      const unsigned long long m0 = __ballot(has0 && k0 == k), m1 = __ballot(has1 && k1 == k);
+      if (has0 && k0 == k) s_rows[o * P + base + __popcll(m0 & lt)] = (unsigned char)lane;
+      if (has1 && k1 == k)
+        s_rows[o * P + base + __popcll(m0) + __popcll(m1 & lt)] = (unsigned char)(lane + 64);
+      if (lane == 0) s_rbeg[o * (P + 1) + k] = base;
+      base += __popcll(m0) + __popcll(m1);
+    }
+    if (lane == 0) {
+      s_rbeg[o * (P + 1) + na] = base;
+      s_na[o] = na;
+    }
+  }
+  __syncthreads();
+
+  const int kq = lane >> 4;
+  unsigned qreg[KP / 4];
+#pragma unroll
+  for (int kk = 0; kk < KP / 4; ++kk) qreg[kk] = s_qidx[4 * kk + kq];
+  for (int sub = 0; sub * CB < nchunk; ++sub) {
+    const int nbk = min(CB, nchunk - sub * CB);
+    if (tid < nbk) {
+      const int ps = Q.gslot[g0 + sub * CB + tid];
+      s_pslot[tid] = ps;
+      s_box[tid] = (int)(Q.cone_key[ps] / (unsigned long long)Q.ngrid);
+    }
+    for (int i = tid; i < NCOL * P * 2; i += blockDim.x) s_y[i] = 0;
+    __syncthreads();
+    // Children present per octant, compacted with a wave ballot.
+    for (int o = wave; o < 8; o += NWAVES) {
+      const int k = lane < nbk ? Q.child[8 * (int64_t)s_box[lane] + o] : -1;
+      const unsigned long long mask = __ballot(k >= 0);
+      if (k >= 0) {
+        const int pos = __popcll(mask & ((1ull << lane) - 1ull));
+        s_nlist[o * CB + pos] = lane;
+        s_child[o * CB + pos] = k;
+      }
+      if (lane == 0) s_no[o] = __popcll(mask);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int acc = 0;
+      for (int o = 0; o < 8; ++o) {
+        s_ipre[o] = acc;
+        acc += s_na[o] * ((s_no[o] * nrhs + 15) / 16);
+      }
+      s_ipre[8] = acc;
+    }
+    // Child cone slots of every (octant, box, child cone), in one batch.
+    for (int idx = tid; idx < 8 * CB * NAMAX; idx += blockDim.x) {
+      const int o = idx / (CB * NAMAX), rem = idx - o * (CB * NAMAX);
+      const int n = rem / NAMAX, k = rem - n * NAMAX;
+      int cs = -1;
+      if (n < s_no[o] && k < s_na[o]) {
+        cs = cone_lookup(S, (unsigned long long)s_child[o * CB + n] * S.ngrid + s_dist[o * P + k]);
+        if (cs < 0) atomicOr(A.err, 1);
+      }
+      s_cslot[idx] = cs;
+    }
+    __syncthreads();
+    // Work items over all octants: (octant o, child cone k, N-tile).  The B
+    // fragments (child cone values of 16 (box, rhs) columns) are loaded once
+    // per item and reused for the M-tiles (node rows) of that child cone.
+    // Operand preparation is branch-free so that the loads batch: padded
+    // columns read a valid cone and are scaled by 0, padded K (q >= P)
+    // points at the zero weight slot, padded rows use a 0 factor.
+    const int nitems = s_ipre[8];
+    for (int item = wave; item < nitems; item += NWAVES) {
+      int o = 0;
+      while (s_ipre[o + 1] <= item) ++o;
+      const int ncols = s_no[o] * nrhs;
+      const int ntn = (ncols + 15) / 16;
+      const int li = item - s_ipre[o];
+      const int k = li / ntn, nt = li - (li / ntn) * ntn;
+      const int rb0 = s_rbeg[o * (P + 1) + k], rlen = s_rbeg[o * (P + 1) + k + 1] - rb0;
+      const int col = nt * 16 + (lane & 15);
+      const bool colok = col < ncols;
+      const int n = colok ? col / nrhs : 0;
+      const int r = colok ? col - n * nrhs : 0;
+      int cs = -1;
+      if (colok) {
+        if (k < NAMAX) {
+          cs = s_cslot[(o * CB + n) * NAMAX + k];
+        } else {
+          cs = cone_lookup(
+              S, (unsigned long long)s_child[o * CB + n] * S.ngrid + s_dist[o * P + k]);
+          if (cs < 0) atomicOr(A.err, 1);
+        }
+      }
+      const T bm = cs >= 0 ? (T)1 : (T)0;
+      const CT* vp = Vc + ((int64_t)(cs >= 0 ? cs : 0) * nrhs + (cs >= 0 ? r : 0)) * P;
+      T br[KP / 4], bi[KP / 4];
+#pragma unroll
+      for (int kk = 0; kk < KP / 4; ++kk) {
+        const int q = min(4 * kk + kq, P - 1);
+        const CT x = vp[q];
+        br[kk] = x.x * bm;
+        bi[kk] = x.y * bm;
+      }
+      const int b = colok ? s_nlist[o * CB + n] : 0;
+      for (int mt = 0; mt * 16 < rlen; ++mt) {
+        // A operand: row m of this tile -> node p; W[p][q] = L_a L_b L_c.
+        const int m = mt * 16 + (lane & 15);
+        const int pa = m < rlen ? (int)s_rows[o * P + rb0 + m] : 0;
+        const T am = m < rlen ? (T)1 : (T)0;
+        const T* L = s_L + (o * P + pa) * NWP;
+        T av[KP / 4];
+#pragma unroll
+        for (int kk = 0; kk < KP / 4; ++kk) {
+          const unsigned qi = qreg[kk];
+          av[kk] = L[qi & 0xff] * L[(qi >> 8) & 0xff] * L[qi >> 16] * am;
+        }
+        // Epilogue operands, fetched before the products.
+        int pe[4];
+        T gce[4], gse[4];
+#pragma unroll
+        for (int r4 = 0; r4 < 4; ++r4) {
+          const int mm = mt * 16 + Mfma<T>::row(lane, r4);
+          pe[r4] = mm < rlen ? (int)s_rows[o * P + rb0 + mm] : -1;
+          const int pp = pe[r4] >= 0 ? pe[r4] : 0;
+          gce[r4] = s_rat[2 * (o * P + pp)];
+          gse[r4] = s_rat[2 * (o * P + pp) + 1];
+        }
+        V4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < KP / 4; ++kk) {
+          accr = Mfma<T>::mma(av[kk], br[kk], accr);
+          acci = Mfma<T>::mma(av[kk], bi[kk], acci);
+        }
+        // Rows -> nodes, columns -> (box, rhs); times the ratio.  Octants
+        // run concurrently on different waves: LDS atomic adds.
+        if (colok) {
+#pragma unroll
+          for (int r4 = 0; r4 < 4; ++r4) {
+            if (pe[r4] >= 0) {
+              T* y = s_y + 2 * ((b * MAXR + r) * P + pe[r4]);
+              atomicAdd(y, accr[r4] * gce[r4] - acci[r4] * gse[r4]);
+              atomicAdd(y + 1, accr[r4] * gse[r4] + acci[r4] * gce[r4]);
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // Write the parent cones of this sub-chunk.
+    for (int idx = tid; idx < nbk * nrhs * P; idx += blockDim.x) {
+      const int b = idx / (nrhs * P);
+      const int rem = idx - b * (nrhs * P);
+      const int r = rem / P, p = rem - (rem / P) * P;
+      CT v;
+      v.x = s_y[2 * ((b * MAXR + r) * P + p)];
+      v.y = s_y[2 * ((b * MAXR + r) * P + p) + 1];
+      Vp[((int64_t)s_pslot[b] * nrhs + r) * P + p] = v;
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Plan-time kernels: relevant cone segments.
 // ---------------------------------------------------------------------------
@@ -646,6 +954,18 @@ __global__ void fill_u64_kernel(unsigned long long* p, int64_t n,
   if (t < n) p[t] = v;
 }
 
+__global__ void fill_i32_kernel(int* p, int64_t n, int v) {
+  int64_t t = gtid();
+  if (t < n) p[t] = v;
+}
+
+// Dense look-up table: table[box * ngrid + gamma] = slot.
+__global__ void scatter_table_kernel(const unsigned long long* __restrict__ keys,
+                                     int64_t n, int* table) {
+  int64_t t = gtid();
+  if (t < n) table[keys[t]] = (int)t;
+}
+
 __global__ void compact_keys_kernel(const unsigned long long* __restrict__ tab,
                                     int64_t cap, unsigned long long* out,
                                     unsigned int* counter) {
@@ -707,6 +1027,19 @@ hipError_t launch_mark(const ApplyArgs& A, int l, int ps, int pa,
   return e;
 }
 
+hipError_t launch_fill_i32(int* p, int64_t n, int v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  fill_i32_kernel<<<nblk(n, 256), 256, 0, st>>>(p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_table(const unsigned long long* keys, int64_t n,
+                                int* table, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  scatter_table_kernel<<<nblk(n, 256), 256, 0, st>>>(keys, n, table);
+  return hipGetLastError();
+}
+
 hipError_t launch_compact(const unsigned long long* tab, int64_t cap,
                           unsigned long long* out, unsigned int* counter,
                           hipStream_t st) {
@@ -749,6 +1082,12 @@ hipError_t sort_keys(unsigned long long* keys, unsigned long long* tmp,
     }                                                              \
   } while (0)
 
+int chunk_boxes(int precision, int nrhs) {
+  const int maxr = nrhs <= 1 ? 1 : kMaxRhs;
+  return kSubChunks *
+         (precision == 0 ? ChunkCols<double, 1>::boxes : ChunkCols<float, 1>::boxes) / maxr;
+}
+
 template <int PS, int PA, typename T, int MAXR>
 static hipError_t apply_impl(const ApplyArgs& A, const void* dens_user,
                              void* out_user, hipStream_t st, Profiler* prof) {
@@ -775,9 +1114,18 @@ static hipError_t apply_impl(const ApplyArgs& A, const void* dens_user,
         IFGF_TIMED(3, (interp_kernel<PS, PA, T, MAXR>
                        <<<nblk(A.n, 256), 256, 0, st>>>(A, l, Vcur, os)));
       if (l + 1 < A.n_steps && A.step_host[l + 1].ncones > 0) {
-        IFGF_TIMED(4, (prop_kernel<PS, PA, T, MAXR>
-                       <<<nblk(A.step_host[l + 1].ncones * P, 256), 256, 0, st>>>(
-                           A, l, Vcur, Vnext)));
+        const StepDev& Qh = A.step_host[l + 1];
+        bool done = false;
+        if constexpr (P <= kMfmaMaxP) {
+          if (Qh.prop_grouped) {
+            IFGF_TIMED(4, (prop_mfma_kernel<PS, PA, T, MAXR>
+                           <<<(unsigned)Qh.nchunks, kMfmaThreads, 0, st>>>(A, l, Vcur, Vnext)));
+            done = true;
+          }
+        }
+        if (!done)
+          IFGF_TIMED(4, (prop_kernel<PS, PA, T, MAXR>
+                         <<<nblk(Qh.ncones * P, 256), 256, 0, st>>>(A, l, Vcur, Vnext)));
         CT* tmp = Vcur;
         Vcur = Vnext;
         Vnext = tmp;

@@ -23,7 +23,7 @@ STATUS = {0: "IFGF_OK", 1: "IFGF_EINVAL", 2: "IFGF_ENOMEM", 3: "IFGF_EDUPLICATE"
 EXPORTED = ["ifgf_default_opts", "ifgf_plan", "ifgf_plan_ex", "ifgf_plan_batched",
             "ifgf_apply", "ifgf_check", "ifgf_set_stream", "ifgf_plan_info",
             "ifgf_partition_counts", "ifgf_destroy", "ifgf_status_string",
-            "ifgf_profile", "ifgf_profile_read"]
+            "ifgf_profile", "ifgf_profile_read", "ifgf_cone_keys"]
 
 STAGES = ["permute_in", "near_field", "leaf", "interpolation", "propagation",
           "permute_out"]
@@ -33,7 +33,9 @@ class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("n_rhs", ctypes.c_int),
                 ("leaf_grid", ctypes.c_int * 3), ("levels", ctypes.c_int),
                 ("stages", ctypes.c_int), ("host_only", ctypes.c_int),
-                ("device", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("device", ctypes.c_int), ("stream", ctypes.c_void_p),
+                ("prop_kernel", ctypes.c_int), ("lookup", ctypes.c_int),
+                ("cone_margin", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -85,6 +87,7 @@ def load_library():
     lib.ifgf_set_stream.argtypes = [P, P]
     lib.ifgf_plan_info.argtypes = [P, ctypes.POINTER(Info)]
     lib.ifgf_partition_counts.argtypes = [P, P]
+    lib.ifgf_cone_keys.argtypes = [P, I, P, I64]
     lib.ifgf_profile.argtypes = [P, I]
     lib.ifgf_profile_read.argtypes = [P, ctypes.POINTER(StageTimes), I]
     lib.ifgf_destroy.argtypes = [P]
@@ -103,7 +106,8 @@ def _check(rc):
         raise IFGFError(rc, load_library().ifgf_status_string(rc).decode())
 
 
-def _opts(precision, n_rhs, leaf_grid, levels, stages, host_only, device):
+def _opts(precision, n_rhs, leaf_grid, levels, stages, host_only, device,
+          cone_margin=None, prop_kernel=0, lookup=0):
     o = Opts()
     _check(load_library().ifgf_default_opts(ctypes.byref(o)))
     o.precision = {"fp64": FP64, "fp32": FP32_MIXED, "mixed": FP32_MIXED,
@@ -114,6 +118,10 @@ def _opts(precision, n_rhs, leaf_grid, levels, stages, host_only, device):
     o.stages = int(stages)
     o.host_only = 1 if host_only else 0
     o.device = -1 if device is None else int(device)
+    if cone_margin is not None:
+        o.cone_margin = float(cone_margin)
+    o.prop_kernel = {"auto": 0, "node": 1, "grouped": 2, 0: 0, 1: 1, 2: 2}[prop_kernel]
+    o.lookup = {"auto": 0, "hash": 1, 0: 0, 1: 1}[lookup]
     return o
 
 
@@ -181,6 +189,14 @@ class Plan:
         _check(load_library().ifgf_profile_read(self._h, ctypes.byref(t), 1 if reset else 0))
         return {s: (t.ms[i], t.launches[i]) for i, s in enumerate(STAGES)}
 
+    def cone_keys(self, step):
+        """Sorted relevant-cone keys box * grid + gamma of step l = D - d."""
+        n = self.info()["cones"][step]
+        out = np.zeros(n, dtype=np.uint64)
+        _check(load_library().ifgf_cone_keys(self._h, int(step),
+                                             out.ctypes.data_as(ctypes.c_void_p), n))
+        return out
+
     def partition_counts(self):
         out = np.zeros(self.n, dtype=np.int64)
         _check(load_library().ifgf_partition_counts(self._h, out.ctypes.data_as(ctypes.c_void_p)))
@@ -206,12 +222,13 @@ class Plan:
 
 def plan(points, kappa, p_s=3, p_ang=5, leaf_size=0.25, precision="fp64",
          n_rhs=1, leaf_grid=(2, 4, 8), levels=0, stages=3, host_only=False,
-         device=None):
+         device=None, cone_margin=None, prop_kernel="auto", lookup="auto"):
     """Plan one instance; points is an (N, 3) float64 array (host)."""
     pts = np.ascontiguousarray(np.asarray(points, dtype=np.float64))
     if pts.ndim != 2 or pts.shape[1] != 3:
         raise ValueError("points must have shape (N, 3)")
-    o = _opts(precision, n_rhs, leaf_grid, levels, stages, host_only, device)
+    o = _opts(precision, n_rhs, leaf_grid, levels, stages, host_only, device,
+              cone_margin, prop_kernel, lookup)
     h = ctypes.c_void_p()
     _check(load_library().ifgf_plan_ex(ctypes.byref(h), pts.ctypes.data_as(ctypes.c_void_p),
                                        pts.shape[0], float(kappa), int(p_s), int(p_ang),
@@ -221,7 +238,8 @@ def plan(points, kappa, p_s=3, p_ang=5, leaf_size=0.25, precision="fp64",
 
 def plan_batched(points_list, kappas, p_s=3, p_ang=5, leaf_size=0.25,
                  precision="fp64", n_rhs=1, leaf_grid=(2, 4, 8), levels=0,
-                 stages=3, host_only=False, device=None):
+                 stages=3, host_only=False, device=None, cone_margin=None,
+                 prop_kernel="auto", lookup="auto"):
     """Plan several independent instances evaluated together by each apply.
 
     Densities and outputs are (n_rhs, sum N_i), instances concatenated.
@@ -231,7 +249,8 @@ def plan_batched(points_list, kappas, p_s=3, p_ang=5, leaf_size=0.25,
     offsets = np.zeros(len(points_list) + 1, dtype=np.int64)
     offsets[1:] = np.cumsum([len(p) for p in points_list])
     kap = np.ascontiguousarray(np.asarray(kappas, dtype=np.float64))
-    o = _opts(precision, n_rhs, leaf_grid, levels, stages, host_only, device)
+    o = _opts(precision, n_rhs, leaf_grid, levels, stages, host_only, device,
+              cone_margin, prop_kernel, lookup)
     h = ctypes.c_void_p()
     _check(load_library().ifgf_plan_batched(
         ctypes.byref(h), len(points_list), offsets.ctypes.data_as(ctypes.c_void_p),

@@ -120,18 +120,21 @@ def test_other_orders_match_oracle(ps, pa):
     assert relerr(g[0], o) <= 1e-10
 
 
+@pytest.mark.parametrize("prop", ["auto", "grouped", "node"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_multi_rhs_equals_single_rhs(precision):
+def test_multi_rhs_equals_single_rhs(precision, prop):
     n = 6000
     p = W.spheroid(n)
     k = W.kappa_oblate_10ppw(n)
     a = W.densities(n, 4, 35)
-    say("multi-rhs", precision)
-    g4, _ = run_gpu(p, a, k, precision=precision)
+    say("multi-rhs", precision, prop)
+    g4, _ = run_gpu(p, a, k, precision=precision, prop_kernel=prop)
     tol = 1e-13 if precision == "fp64" else 1e-6
     for r in range(4):
-        g1, _ = run_gpu(p, a[r:r + 1], k, precision=precision)
+        g1, _ = run_gpu(p, a[r:r + 1], k, precision=precision, prop_kernel=prop)
         assert relerr(g4[r], g1[0]) <= tol
+    o = oracle.ifgf(p, a[2], k, leaf_grid=(2, 4, 8))
+    assert relerr(g4[2], o) <= (1e-10 if precision == "fp64" else 2e-5)
 
 
 def test_batched_equals_separate_plans():
@@ -192,3 +195,44 @@ def test_sphere_321k_sampled_vs_direct_sum(precision):
     err = relerr(g[0][w.targets], ref)
     print(f"sphere_321k {precision} rel-err {err:.3e}", flush=True)
     assert err <= 1e-4
+
+
+@pytest.mark.parametrize("geom", ["sphere", "oblate"])
+def test_relevant_cones_match_oracle_exactly(geom):
+    """Index work, bit-exact: with no boundary margin the GPU's relevant
+    cone segments (eq. relevantconesegments, point-based) are exactly the
+    oracle's, key by key, at every level; with the default margin they are
+    a superset."""
+    import paper_2112_15198_amd as ifgf
+    if geom == "sphere":
+        p, k = W.fibonacci_sphere(5024), 4 * math.pi
+    else:
+        p, k = W.spheroid(9000), W.kappa_oblate_10ppw(9000)
+    say("cone keys", geom)
+    exact = ifgf.plan(p, k, cone_margin=0.0)
+    loose = ifgf.plan(p, k)
+    D = exact.info()["D"]
+    for l in range(D - 2):
+        ok = oracle.cone_keys(p, k, D - l, leaf_grid=(2, 4, 8))
+        ge = exact.cone_keys(l)
+        np.testing.assert_array_equal(ge, ok)
+        gl = loose.cone_keys(l)
+        assert np.isin(ok, gl).all()
+    exact.close()
+    loose.close()
+
+
+@pytest.mark.parametrize("prop,lookup", [("node", "auto"), ("grouped", "auto"),
+                                         ("grouped", "hash"), ("node", "hash")])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 2e-5)])
+def test_kernel_variants_match_oracle(prop, lookup, precision, tol):
+    """Per-node and grouped propagation, dense and hashed cone look-up: all
+    agree with the oracle IFGF (FP64: 1e-10; FP32-mixed: 2e-5, its rounding)."""
+    n = 7000
+    p = W.fibonacci_sphere(n)
+    k = W.kappa_sphere_10ppw(n)
+    a = W.densities(n, 1, 37)
+    say("variant", prop, lookup, precision)
+    g, _ = run_gpu(p, a, k, precision=precision, prop_kernel=prop, lookup=lookup)
+    o = oracle.ifgf(p, a[0], k, leaf_grid=(2, 4, 8))
+    assert relerr(g[0], o) <= tol
