@@ -1,8 +1,10 @@
 """Benchmark of the IFGF Helmholtz matvec on one MI355X.
 
-A step is one complete ifgf_apply (permute in, near field, leaf
-evaluations, interpolation and propagation at every level, permute out)
-over one set of densities already resident in HBM.
+A step is one complete apply (permute in, near field, leaf evaluations,
+interpolation and propagation at every level, permute out) over one set of
+densities already resident in HBM, replayed as one captured HIP graph; the
+eager (launch-by-launch) time is reported beside it.  The plan is built
+with the autotuner on (per-level choice of propagation kernel).
 
 Workload: N = 321,536 points on the unit sphere (Fibonacci lattice),
 kappa = 32 pi, complex densities iid U(-1,1), (P_s, P_ang) = (3, 5), leaf
@@ -10,13 +12,15 @@ cone grid (2,4,8), one right-hand side.  The headline figure is the
 FP32-mixed path; the plain FP64 path is timed on the same GPU beside it.
 
 Prints one JSON line:
-  value      = N^2 / t (FP32-mixed), t = mean apply time
+  value      = N^2 * n_rhs / t (FP32-mixed), t = mean apply time (sum of
+               N_i^2 over the instances of a batched workload)
   fp64       = the same for the FP64 path
   rel_err    = relative l2 error against the FP64 direct sum on 4,096
                sampled targets (eq. errorcomputation of the paper)
-  roofline   = the dominant kernel (propagation): algorithmic FLOP per
-               launch over its mean HIP-event launch time, against the
-               MI355X vector peak of its precision
+  roofline   = the dominant kernel: algorithmic FLOP per launch over its
+               mean HIP-event launch time (eager applies), against the
+               MI355X peak of its precision (matrix cores for the
+               matrix-core propagation, vector ALUs otherwise)
   cpu_baseline = the CPU oracle (FP64 direct sum, OpenMP) on the sampled
                targets, scaled to N^2/s
 """
@@ -37,7 +41,8 @@ if ROOT not in sys.path:
 
 METRIC = "IFGF matvec ms & N^2/t at rel-err<=1e-4 vs FP64 direct: FP32-mixed vs FP64"
 
-# MI355X published peaks (dense): vector FP32 157.3 TFLOP/s, FP64 78.6.
+# MI355X published dense peaks: FP32 157.3 TFLOP/s, FP64 78.6 (vector and
+# matrix cores alike).
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
 
 
@@ -48,28 +53,37 @@ def flops_per_eval(P):
     return 4 * P + 8
 
 
-def time_applies(pl, a, steps, warmup, profile):
+def time_applies(pl, a, steps, warmup, graph):
+    """Mean ms per apply over `steps` applies (after `warmup`), bracketed by
+    torch.cuda.synchronize; graph=True replays the captured apply."""
     import torch
+    out = torch.empty_like(a)
     for _ in range(warmup):
-        pl.apply(a)
+        pl.apply(a, out=out, graph=graph)
     pl.check()
-    pl.profile_read(reset=True)
-    if profile:
-        pl.profile(True)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
-    out = None
     for _ in range(steps):
-        out = pl.apply(a)
+        pl.apply(a, out=out, graph=graph)
     e1.record()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    stages = pl.profile_read(reset=True) if profile else {}
-    pl.profile(False)
     pl.check()
-    return ms, out, stages
+    return e0.elapsed_time(e1) / steps, out
+
+
+def stage_times(pl, a, steps):
+    """Per-stage kernel times (HIP events around every launch), eager applies."""
+    import torch
+    out = torch.empty_like(a)
+    pl.profile_read(reset=True)
+    pl.profile(True)
+    for _ in range(steps):
+        pl.apply(a, out=out)
+    st = pl.profile_read(reset=True)
+    pl.profile(False)
+    return st
 
 
 def main():
@@ -79,6 +93,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="sphere_321k")
     ap.add_argument("--precision", choices=["both", "fp32", "fp64"], default="both")
+    ap.add_argument("--samples-batch", type=int, default=256,
+                    help="error-check targets per instance of a batched workload")
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the CPU oracle (baseline and error check)")
     args = ap.parse_args()
@@ -92,26 +108,39 @@ def main():
     from paper_2112_15198_amd import workloads as W
 
     w = W.make(args.workload)
-    n = w.points.shape[0]
-    n_rhs = w.dens.shape[0]
+    batch = isinstance(w, list)
+    insts = w if batch else [w]
+    n = sum(x.points.shape[0] for x in insts)
+    n2 = float(sum(float(x.points.shape[0]) ** 2 for x in insts))
+    n_rhs = insts[0].dens.shape[0]
+    dens = np.concatenate([x.dens for x in insts], axis=1)
     p_s, p_ang, grid = 3, 5, (2, 4, 8)
     P = p_s * p_ang * p_ang
     precs = ["fp32", "fp64"] if args.precision == "both" else [args.precision]
     res = {}
     for prec in precs:
         t0 = time.perf_counter()
-        pl = ifgf.plan(w.points, w.kappa, p_s=p_s, p_ang=p_ang, precision=prec,
-                       n_rhs=n_rhs, leaf_grid=grid)
+        if batch:
+            pl = ifgf.plan_batched([x.points for x in insts], [x.kappa for x in insts],
+                                   p_s=p_s, p_ang=p_ang, precision=prec, n_rhs=n_rhs,
+                                   leaf_grid=grid, autotune=True)
+        else:
+            pl = ifgf.plan(w.points, w.kappa, p_s=p_s, p_ang=p_ang, precision=prec,
+                           n_rhs=n_rhs, leaf_grid=grid, autotune=True)
         plan_s = time.perf_counter() - t0
         dt = torch.complex64 if prec == "fp32" else torch.complex128
-        a = torch.from_numpy(w.dens).to(dt).cuda()
-        ms, out, stages = time_applies(pl, a, args.steps, args.warmup, profile=True)
+        a = torch.from_numpy(dens).to(dt).cuda()
+        ms_eager, _ = time_applies(pl, a, args.steps, args.warmup, graph=False)
+        stages = stage_times(pl, a, args.steps)
+        ms, out = time_applies(pl, a, args.steps, args.warmup, graph=True)
         info = pl.info()
-        res[prec] = {"ms": ms, "out": out.cpu().numpy().astype(np.complex128),
+        res[prec] = {"ms": ms, "ms_eager": ms_eager,
+                     "out": out.cpu().numpy().astype(np.complex128),
                      "stages": stages, "info": info, "plan_s": plan_s}
-        print(f"# {prec}: {ms:.3f} ms/apply, plan {plan_s:.2f} s, "
+        print(f"# {prec}: {ms:.3f} ms/apply (graph), {ms_eager:.3f} eager, plan {plan_s:.2f} s, "
               + ", ".join(f"{k} {v[0] / max(v[1], 1):.3f} ms x{v[1] // args.steps}"
-                          for k, v in stages.items()), file=sys.stderr, flush=True)
+                          for k, v in stages.items())
+              + f"; prop kernels {info['prop_mode']}", file=sys.stderr, flush=True)
         pl.close()
         del a, out
         torch.cuda.empty_cache()
@@ -119,7 +148,8 @@ def main():
     head = "fp32" if "fp32" in res else "fp64"
     R = res[head]
     ms = R["ms"]
-    value = n * n / (ms * 1e-3)
+    # Matvec-equivalents: one apply evaluates n_rhs operators.
+    value = n2 * n_rhs / (ms * 1e-3)
 
     # Dominant kernel: the stage with the largest summed time.
     st = R["stages"]
@@ -127,10 +157,13 @@ def main():
     info = R["info"]
     launches = st[dom][1] / args.steps
     avg_ms = st[dom][0] / st[dom][1]
-    if dom == "propagation":
-        units = sum(info["prop_pairs"])
+    bound = "alu"
+    if dom in ("propagation", "propagation_mfma"):
+        mode = 2 if dom == "propagation_mfma" else 1
+        units = sum(pp for pp, md in zip(info["prop_pairs"], info["prop_mode"]) if md == mode)
         flop = units * n_rhs * flops_per_eval(P)
         unit_txt = "(parent-cone node, relevant child) evaluations"
+        bound = "mfma" if mode == 2 else "alu"
     elif dom == "interpolation":
         units = sum(info["cousin_pairs"])
         flop = units * n_rhs * flops_per_eval(P)
@@ -146,55 +179,75 @@ def main():
     per_launch = flop / launches
     achieved = per_launch / (avg_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[head]
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
+    roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
                 "kernel": dom, "launches_per_step": launches,
                 "avg_launch_ms": round(avg_ms, 4),
                 "flop_per_launch": per_launch,
                 "units_per_step": units,
-                "flop_per_unit_per_rhs": flops_per_eval(P) if dom in ("propagation", "interpolation") else 30,
+                "flop_per_unit_per_rhs": flops_per_eval(P) if dom.startswith("prop") or dom == "interpolation" else 30,
                 "unit_desc": unit_txt}
 
+    if batch:
+        cfg = {"workload": args.workload, "instances": len(insts), "N_total": n,
+               "sum_N2": n2, "N_min": min(x.points.shape[0] for x in insts),
+               "N_max": max(x.points.shape[0] for x in insts),
+               "geometry": "spheres and (1,1,0.25) spheroids, Fibonacci lattices, ~10 ppw"}
+    else:
+        cfg = {"workload": args.workload, "N": n, "kappa": w.kappa,
+               "geometry": ("unit-sphere" if "sphere" in args.workload else
+                            "(1,1,0.25) spheroid") + " Fibonacci lattice"}
+    cfg.update({"p_s": p_s, "p_ang": p_ang, "leaf_grid": list(grid), "n_rhs": n_rhs,
+                "D": info["D"], "precision": "fp32-mixed" if head == "fp32" else "fp64",
+                "apply": "captured HIP graph"})
     line = {"metric": METRIC, "value": value, "unit": "N^2/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f32-mixed" if head == "fp32" else "f64", "data": "synthetic",
-            "config": {"workload": args.workload, "N": n, "kappa": w.kappa,
-                       "geometry": "unit-sphere Fibonacci lattice",
-                       "p_s": p_s, "p_ang": p_ang, "leaf_grid": list(grid),
-                       "n_rhs": n_rhs, "D": info["D"],
-                       "precision": "fp32-mixed" if head == "fp32" else "fp64"},
-            "plan_s": R["plan_s"],
+            "config": cfg,
+            "plan_s": R["plan_s"], "ms_per_step_eager": R["ms_eager"],
+            "prop_kernel_per_level": info["prop_mode"],
             "stages_ms": {k: round(v[0] / args.steps, 4) for k, v in st.items()},
             "roofline": roofline}
     if "fp64" in res and head != "fp64":
-        line["fp64"] = {"ms_per_step": res["fp64"]["ms"],
-                        "value": n * n / (res["fp64"]["ms"] * 1e-3),
+        line["fp64"] = {"ms_per_step": res["fp64"]["ms"], "ms_per_step_eager": res["fp64"]["ms_eager"],
+                        "value": n2 * n_rhs / (res["fp64"]["ms"] * 1e-3),
                         "stages_ms": {k: round(v[0] / args.steps, 4)
                                       for k, v in res["fp64"]["stages"].items()}}
         line["speedup_fp32_mixed_over_fp64"] = res["fp64"]["ms"] / ms
 
     if not args.no_cpu:
         # CPU baseline leg: the oracle's FP64 direct sum at the sampled
-        # targets, which is also the reference for the error estimate.
+        # targets, which is also the reference for the error estimate
+        # (relative l2, eq. errorcomputation; max over RHS and instances).
         import oracle
-        tg = w.targets
         threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
-        t0 = time.perf_counter()
-        ref = oracle.direct_sum(w.points, w.dens[0], w.kappa, tg)
-        t_cpu = time.perf_counter() - t0
+        per_inst = args.samples_batch if batch else None
+        t_cpu, pairs = 0.0, 0
+        errs = {prec: 0.0 for prec in res}
+        off = 0
+        for x in insts:
+            ni = x.points.shape[0]
+            tg = x.targets if per_inst is None else x.targets[:per_inst]
+            for r in range(n_rhs):
+                t0 = time.perf_counter()
+                ref = oracle.direct_sum(x.points, x.dens[r], x.kappa, tg)
+                t_cpu += time.perf_counter() - t0
+                pairs += ni * len(tg)
+                for prec in res:
+                    g = res[prec]["out"][r, off:off + ni][tg]
+                    e = float(np.linalg.norm(g - ref) / np.linalg.norm(ref))
+                    errs[prec] = max(errs[prec], e)
+            off += ni
         line["cpu_baseline"] = {
-            "value": n * len(tg) / t_cpu, "unit": "N^2/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"FP64 direct sum (eq. field1) at {len(tg)} seeded targets x all "
-                      f"{n} sources; full-matvec time extrapolated as t*N/{len(tg)}",
+            "value": pairs / t_cpu, "unit": "N^2/s", "cores": threads, "kind": "oracle",
+            "sample": (f"FP64 direct sum (eq. field1) at the sampled targets x all sources "
+                       f"({pairs} pairs, {len(insts)} instance(s), {n_rhs} RHS); "
+                       f"full-matvec time extrapolated pro rata"),
             "seconds": t_cpu}
-        for prec in res:
-            e = float(np.linalg.norm(res[prec]["out"][0][tg] - ref) / np.linalg.norm(ref))
-            if prec == head:
-                line["rel_err"] = e
-            else:
-                line["fp64"]["rel_err"] = e
+        line["rel_err"] = errs[head]
+        if "fp64" in line:
+            line["fp64"]["rel_err"] = errs["fp64"]
     print(json.dumps(line), flush=True)
 
 

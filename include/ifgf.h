@@ -75,6 +75,9 @@ typedef struct ifgf_opts {
   int lookup;       /* cone look-up: 0 dense tables where a level's table
                        (boxes x cone grid) has <= 2^28 entries, hash tables
                        elsewhere; 1 hash tables everywhere */
+  int autotune;     /* 1: at plan time, time both propagation kernels on
+                       every level where both apply and keep the faster
+                       (overrides prop_kernel there) */
   double cone_margin; /* a point within cone_margin cone widths of a cone
                        boundary also marks the adjacent cone relevant, so
                        that look-ups along other rounding paths never miss;
@@ -98,6 +101,11 @@ typedef struct ifgf_info {
   int64_t prop_pairs[IFGF_MAX_LEVELS]; /* (parent-cone node, relevant child)
                                          evaluations of Propagation into
                                          step l (l >= 1) */
+  int prop_mode[IFGF_MAX_LEVELS];      /* kernel of Propagation into step l:
+                                         1 per-node, 2 matrix-core */
+  float autotune_ms[IFGF_MAX_LEVELS][2]; /* autotuner timings of Propagation
+                                         into step l: per-node, matrix-core
+                                         (0 when not tuned) */
   int64_t leaf_pairs;     /* (leaf-cone node, source) evaluations of
                              LevelDEvaluations */
   int64_t near_pairs;     /* (target, source) near-field pairs, self included */
@@ -142,6 +150,13 @@ ifgf_status ifgf_plan_batched(ifgf_plan_t* plan, int n_inst,
  * host; one apply at a time per plan (not re-entrant). */
 ifgf_status ifgf_apply(ifgf_plan_t plan, const void* densities, void* out);
 
+/* As ifgf_apply, through a HIP graph: the first call for a (densities,
+ * out) pair captures the whole apply (every kernel launch of every level)
+ * into a graph and instantiates it; later calls with the same pointers
+ * replay it with one hipGraphLaunch on the plan's stream.  Other pointers
+ * re-capture.  Profiling is not applied to graph launches. */
+ifgf_status ifgf_apply_graph(ifgf_plan_t plan, const void* densities, void* out);
+
 /* Wait for the plan's stream and report whether any cone look-up of the
  * previous applies missed (IFGF_ELOOKUP); clears the flag. */
 ifgf_status ifgf_check(ifgf_plan_t plan);
@@ -155,9 +170,10 @@ typedef enum {
   IFGF_STAGE_NEAR_FIELD = 1,
   IFGF_STAGE_LEAF = 2,          /* LevelDEvaluations */
   IFGF_STAGE_INTERPOLATION = 3, /* Interpolation(d), all levels */
-  IFGF_STAGE_PROPAGATION = 4,   /* Propagation(d), all levels */
+  IFGF_STAGE_PROPAGATION = 4,   /* Propagation(d), per-node kernel levels */
   IFGF_STAGE_PERMUTE_OUT = 5,
-  IFGF_N_STAGES = 6
+  IFGF_STAGE_PROPAGATION_MFMA = 6, /* Propagation(d), matrix-core levels */
+  IFGF_N_STAGES = 7
 } ifgf_stage;
 
 typedef struct ifgf_stage_times {

@@ -67,6 +67,11 @@ struct ifgf_plan_s {
   int prof_pending = 0;
   double prof_ms[IFGF_N_STAGES] = {0};
   int64_t prof_launches[IFGF_N_STAGES] = {0};
+  // Captured apply.
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  const void* g_dens = nullptr;
+  void* g_out = nullptr;
 
   template <class T>
   T* dalloc(int64_t count) {
@@ -97,6 +102,8 @@ struct ifgf_plan_s {
       (void)hipEventDestroy(r.a);
       (void)hipEventDestroy(r.b);
     }
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
   }
 };
 
@@ -142,6 +149,45 @@ static void cheb_nodes(int n, double* t, double* w) {
       if (m != j) p *= (t[j] - t[m]);
     w[j] = 1.0 / p;
   }
+}
+
+// Time both propagation kernels on every level where both apply (zeroed
+// cone values: the kernels' work does not depend on the values) and keep
+// the faster one.
+static void autotune(ifgf_plan_s* P) {
+  ApplyArgs& A = P->A;
+  hipStream_t st = P->stream;
+  const int PP = P->p_s * P->p_ang * P->p_ang;
+  if (PP > kMfmaMaxP) return;
+  size_t csize = P->opts.precision == IFGF_FP64 ? 16 : 8;
+  int64_t maxc = 1;
+  for (int l = 0; l < A.n_steps; ++l) maxc = std::max<int64_t>(maxc, P->steps_h[l].ncones);
+  HIP_TRY(hipMemsetAsync(A.vbuf[0], 0, maxc * A.nrhs * PP * csize, st));
+  HIP_TRY(hipMemsetAsync(A.vbuf[1], 0, maxc * A.nrhs * PP * csize, st));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  for (int l = 0; l + 1 < A.n_steps; ++l) {
+    StepDev& Q = P->steps_h[l + 1];
+    if (Q.ncones == 0 || Q.nchunks == 0) continue;
+    float best[2] = {0, 0};
+    for (int g = 0; g < 2; ++g) {
+      HIP_TRY(launch_prop_level(A, l, P->p_s, P->p_ang, P->opts.precision, g == 1, st));
+      HIP_TRY(hipEventRecord(e0, st));
+      for (int rep = 0; rep < 2; ++rep)
+        HIP_TRY(launch_prop_level(A, l, P->p_s, P->p_ang, P->opts.precision, g == 1, st));
+      HIP_TRY(hipEventRecord(e1, st));
+      HIP_TRY(hipEventSynchronize(e1));
+      HIP_TRY(hipEventElapsedTime(&best[g], e0, e1));
+    }
+    Q.prop_grouped = best[1] < best[0] ? 1 : 0;
+    P->info.autotune_ms[l + 1][0] = best[0] / 2;
+    P->info.autotune_ms[l + 1][1] = best[1] / 2;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIP_TRY(hipMemcpy(P->steps_d, P->steps_h.data(), sizeof(StepDev) * A.n_steps,
+                    hipMemcpyHostToDevice));
 }
 
 static void build_device(ifgf_plan_s* P) {
@@ -324,7 +370,7 @@ static void build_device(ifgf_plan_s* P) {
         double mean = (double)count / (double)std::max<int64_t>(groups, 1);
         int mode = P->opts.prop_kernel;
         D.prop_grouped = PP <= kMfmaMaxP && (mode == 2 || (mode == 0 && mean >= 32.0));
-        if (D.prop_grouped) {
+        if (PP <= kMfmaMaxP && (D.prop_grouped || P->opts.autotune)) {
           D.gslot = P->upload(order);
           D.chunk_start = P->upload(cstart);
           D.chunk_len = P->upload(clen);
@@ -363,6 +409,7 @@ static void build_device(ifgf_plan_s* P) {
   A.dens_sorted = P->dalloc<char>(m.n * A.nrhs * (int64_t)csize);
   A.out_sorted = P->dalloc<char>(m.n * A.nrhs * (int64_t)csize);
   HIP_TRY(hipStreamSynchronize(st));
+  if (P->opts.autotune) autotune(P);
   P->device_ready = true;
 }
 
@@ -386,6 +433,7 @@ static void fill_info(ifgf_plan_s* P) {
     I.cousin_pairs[l] = pairs;
     I.grid[l] = (int64_t)(P->opts.leaf_grid[0] << l) * (P->opts.leaf_grid[1] << l) *
                 (P->opts.leaf_grid[2] << l);
+    I.prop_mode[l] = (l >= 1 && P->device_ready) ? (P->steps_h[l].prop_grouped ? 2 : 1) : 0;
   }
   I.near_pairs = m.near_pairs;
   I.device_bytes = P->bytes;
@@ -521,6 +569,42 @@ ifgf_status ifgf_apply(ifgf_plan_t P, const void* dens, void* out) {
   if (pp) P->prof_pending = prof.n;
   if (e != hipSuccess)
     return fail(IFGF_EHIP, std::string("apply: ") + hipGetErrorString(e));
+  return IFGF_OK;
+}
+
+ifgf_status ifgf_apply_graph(ifgf_plan_t P, const void* dens, void* out) {
+  if (!P || !dens || !out) return fail(IFGF_EINVAL, "null argument");
+  if (!P->device_ready) return fail(IFGF_EINVAL, "plan was built host-only");
+  hipError_t e = hipSetDevice(P->device);
+  if (e == hipSuccess && (!P->gexec || P->g_dens != dens || P->g_out != out)) {
+    if (P->gexec) {
+      (void)hipGraphExecDestroy(P->gexec);
+      P->gexec = nullptr;
+    }
+    // Capture on a stream of the library's own; the null stream cannot be
+    // captured.  Work already queued on the plan's stream is ordered
+    // before the first launch by the launch itself.
+    if (!P->cap_stream) e = hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking);
+    hipGraph_t graph = nullptr;
+    if (e == hipSuccess) e = hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+      hipError_t le = launch_apply(P->A, P->p_s, P->p_ang, P->opts.precision, dens, out,
+                                   P->cap_stream, nullptr);
+      e = hipStreamEndCapture(P->cap_stream, &graph);
+      if (e == hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&P->gexec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e == hipSuccess) {
+      P->g_dens = dens;
+      P->g_out = out;
+    } else {
+      P->gexec = nullptr;
+    }
+  }
+  if (e == hipSuccess) e = hipGraphLaunch(P->gexec, P->stream);
+  if (e != hipSuccess)
+    return fail(IFGF_EHIP, std::string("apply_graph: ") + hipGetErrorString(e));
   return IFGF_OK;
 }
 

@@ -128,6 +128,10 @@ hipError_t launch_build_lookup(const unsigned long long* keys, int64_t n,
 hipError_t sort_keys(unsigned long long* keys, unsigned long long* tmp,
                      int64_t n, int end_bit, void* scratch,
                      size_t* scratch_bytes, hipStream_t st);
+// One Propagation launch (step l -> l + 1) with the chosen kernel
+// (grouped = matrix-core form), for timing at plan time.
+hipError_t launch_prop_level(const ApplyArgs& A, int l, int ps, int pa,
+                             int precision, bool grouped, hipStream_t st);
 hipError_t launch_apply(const ApplyArgs& A, int ps, int pa, int precision,
                         const void* dens_user, void* out_user, hipStream_t st,
                         Profiler* prof);

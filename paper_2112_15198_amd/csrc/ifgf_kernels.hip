@@ -1118,7 +1118,7 @@ static hipError_t apply_impl(const ApplyArgs& A, const void* dens_user,
         bool done = false;
         if constexpr (P <= kMfmaMaxP) {
           if (Qh.prop_grouped) {
-            IFGF_TIMED(4, (prop_mfma_kernel<PS, PA, T, MAXR>
+            IFGF_TIMED(6, (prop_mfma_kernel<PS, PA, T, MAXR>
                            <<<(unsigned)Qh.nchunks, kMfmaThreads, 0, st>>>(A, l, Vcur, Vnext)));
             done = true;
           }
@@ -1135,6 +1135,42 @@ static hipError_t apply_impl(const ApplyArgs& A, const void* dens_user,
   IFGF_TIMED(5, (perm_out_kernel<T><<<nblk(nr, 256), 256, 0, st>>>(
                     os, (CT*)out_user, A.perm, A.n, A.nrhs)));
   return hipGetLastError();
+}
+
+template <int PS, int PA, typename T, int MAXR>
+static hipError_t prop_level_impl(const ApplyArgs& A, int l, bool grouped,
+                                  hipStream_t st) {
+  typedef typename C2<T>::type CT;
+  constexpr int P = PS * PA * PA;
+  const StepDev& Qh = A.step_host[l + 1];
+  CT* Vc = (CT*)A.vbuf[0];
+  CT* Vp = (CT*)A.vbuf[1];
+  if (Qh.ncones <= 0) return hipSuccess;
+  if constexpr (P <= kMfmaMaxP) {
+    if (grouped && Qh.nchunks > 0) {
+      prop_mfma_kernel<PS, PA, T, MAXR><<<(unsigned)Qh.nchunks, kMfmaThreads, 0, st>>>(A, l, Vc, Vp);
+      return hipGetLastError();
+    }
+  }
+  prop_kernel<PS, PA, T, MAXR><<<nblk(Qh.ncones * P, 256), 256, 0, st>>>(A, l, Vc, Vp);
+  return hipGetLastError();
+}
+
+hipError_t launch_prop_level(const ApplyArgs& A, int l, int ps, int pa,
+                             int precision, bool grouped, hipStream_t st) {
+#define IFGF_PL(PS_, PA_)                                                      \
+  if (ps == PS_ && pa == PA_) {                                                \
+    if (precision == 0)                                                        \
+      return A.nrhs <= 1 ? prop_level_impl<PS_, PA_, double, 1>(A, l, grouped, st) \
+                         : prop_level_impl<PS_, PA_, double, kMaxRhs>(A, l, grouped, st); \
+    return A.nrhs <= 1 ? prop_level_impl<PS_, PA_, float, 1>(A, l, grouped, st) \
+                       : prop_level_impl<PS_, PA_, float, kMaxRhs>(A, l, grouped, st); \
+  }
+  IFGF_PL(3, 5)
+  IFGF_PL(2, 3)
+  IFGF_PL(5, 7)
+#undef IFGF_PL
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_apply(const ApplyArgs& A, int ps, int pa, int precision,

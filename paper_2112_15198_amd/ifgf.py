@@ -23,10 +23,11 @@ STATUS = {0: "IFGF_OK", 1: "IFGF_EINVAL", 2: "IFGF_ENOMEM", 3: "IFGF_EDUPLICATE"
 EXPORTED = ["ifgf_default_opts", "ifgf_plan", "ifgf_plan_ex", "ifgf_plan_batched",
             "ifgf_apply", "ifgf_check", "ifgf_set_stream", "ifgf_plan_info",
             "ifgf_partition_counts", "ifgf_destroy", "ifgf_status_string",
-            "ifgf_profile", "ifgf_profile_read", "ifgf_cone_keys"]
+            "ifgf_profile", "ifgf_profile_read", "ifgf_cone_keys",
+            "ifgf_apply_graph"]
 
 STAGES = ["permute_in", "near_field", "leaf", "interpolation", "propagation",
-          "permute_out"]
+          "permute_out", "propagation_mfma"]
 
 
 class Opts(ctypes.Structure):
@@ -35,7 +36,7 @@ class Opts(ctypes.Structure):
                 ("stages", ctypes.c_int), ("host_only", ctypes.c_int),
                 ("device", ctypes.c_int), ("stream", ctypes.c_void_p),
                 ("prop_kernel", ctypes.c_int), ("lookup", ctypes.c_int),
-                ("cone_margin", ctypes.c_double)]
+                ("autotune", ctypes.c_int), ("cone_margin", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -48,6 +49,8 @@ class Info(ctypes.Structure):
                 ("cousin_pairs", ctypes.c_int64 * IFGF_MAX_LEVELS),
                 ("grid", ctypes.c_int64 * IFGF_MAX_LEVELS),
                 ("prop_pairs", ctypes.c_int64 * IFGF_MAX_LEVELS),
+                ("prop_mode", ctypes.c_int * IFGF_MAX_LEVELS),
+                ("autotune_ms", (ctypes.c_float * 2) * IFGF_MAX_LEVELS),
                 ("leaf_pairs", ctypes.c_int64),
                 ("near_pairs", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("plan_seconds", ctypes.c_double)]
@@ -83,6 +86,7 @@ def load_library():
     lib.ifgf_plan_batched.argtypes = [ctypes.POINTER(P), I, P, P, P, I, I, D,
                                       ctypes.POINTER(Opts)]
     lib.ifgf_apply.argtypes = [P, P, P]
+    lib.ifgf_apply_graph.argtypes = [P, P, P]
     lib.ifgf_check.argtypes = [P]
     lib.ifgf_set_stream.argtypes = [P, P]
     lib.ifgf_plan_info.argtypes = [P, ctypes.POINTER(Info)]
@@ -107,7 +111,7 @@ def _check(rc):
 
 
 def _opts(precision, n_rhs, leaf_grid, levels, stages, host_only, device,
-          cone_margin=None, prop_kernel=0, lookup=0):
+          cone_margin=None, prop_kernel=0, lookup=0, autotune=False):
     o = Opts()
     _check(load_library().ifgf_default_opts(ctypes.byref(o)))
     o.precision = {"fp64": FP64, "fp32": FP32_MIXED, "mixed": FP32_MIXED,
@@ -122,6 +126,7 @@ def _opts(precision, n_rhs, leaf_grid, levels, stages, host_only, device,
         o.cone_margin = float(cone_margin)
     o.prop_kernel = {"auto": 0, "node": 1, "grouped": 2, 0: 0, 1: 1, 2: 2}[prop_kernel]
     o.lookup = {"auto": 0, "hash": 1, 0: 0, 1: 1}[lookup]
+    o.autotune = 1 if autotune else 0
     return o
 
 
@@ -143,8 +148,11 @@ class Plan:
         import torch
         return torch.complex128 if self.precision == FP64 else torch.complex64
 
-    def apply(self, dens, out=None, check=False):
-        """dens: CUDA tensor (n_rhs, N) or (N,) of the plan's complex dtype."""
+    def apply(self, dens, out=None, check=False, graph=False):
+        """dens: CUDA tensor (n_rhs, N) or (N,) of the plan's complex dtype.
+
+        graph=True replays a HIP graph of the whole apply, captured on the
+        first call for this (dens, out) pair."""
         import torch
         if self._h is None:
             raise ValueError("plan is closed")
@@ -157,8 +165,8 @@ class Plan:
             out = torch.empty_like(dens)
         lib = load_library()
         _check(lib.ifgf_set_stream(self._h, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
-        _check(lib.ifgf_apply(self._h, ctypes.c_void_p(dens.data_ptr()),
-                              ctypes.c_void_p(out.data_ptr())))
+        fn = lib.ifgf_apply_graph if graph else lib.ifgf_apply
+        _check(fn(self._h, ctypes.c_void_p(dens.data_ptr()), ctypes.c_void_p(out.data_ptr())))
         if check:
             self.check()
         return out.reshape(shape)
@@ -176,6 +184,8 @@ class Plan:
                 "boxes": list(inf.boxes[:L]), "cones": list(inf.cones[:L]),
                 "cousin_pairs": list(inf.cousin_pairs[:L]), "grid": list(inf.grid[:L]),
                 "prop_pairs": list(inf.prop_pairs[:L]), "leaf_pairs": inf.leaf_pairs,
+                "prop_mode": list(inf.prop_mode[:L]),
+                "autotune_ms": [tuple(inf.autotune_ms[l]) for l in range(L)],
                 "near_pairs": inf.near_pairs, "device_bytes": inf.device_bytes,
                 "plan_seconds": inf.plan_seconds}
 
@@ -222,13 +232,14 @@ class Plan:
 
 def plan(points, kappa, p_s=3, p_ang=5, leaf_size=0.25, precision="fp64",
          n_rhs=1, leaf_grid=(2, 4, 8), levels=0, stages=3, host_only=False,
-         device=None, cone_margin=None, prop_kernel="auto", lookup="auto"):
+         device=None, cone_margin=None, prop_kernel="auto", lookup="auto",
+         autotune=False):
     """Plan one instance; points is an (N, 3) float64 array (host)."""
     pts = np.ascontiguousarray(np.asarray(points, dtype=np.float64))
     if pts.ndim != 2 or pts.shape[1] != 3:
         raise ValueError("points must have shape (N, 3)")
     o = _opts(precision, n_rhs, leaf_grid, levels, stages, host_only, device,
-              cone_margin, prop_kernel, lookup)
+              cone_margin, prop_kernel, lookup, autotune)
     h = ctypes.c_void_p()
     _check(load_library().ifgf_plan_ex(ctypes.byref(h), pts.ctypes.data_as(ctypes.c_void_p),
                                        pts.shape[0], float(kappa), int(p_s), int(p_ang),
@@ -239,7 +250,7 @@ def plan(points, kappa, p_s=3, p_ang=5, leaf_size=0.25, precision="fp64",
 def plan_batched(points_list, kappas, p_s=3, p_ang=5, leaf_size=0.25,
                  precision="fp64", n_rhs=1, leaf_grid=(2, 4, 8), levels=0,
                  stages=3, host_only=False, device=None, cone_margin=None,
-                 prop_kernel="auto", lookup="auto"):
+                 prop_kernel="auto", lookup="auto", autotune=False):
     """Plan several independent instances evaluated together by each apply.
 
     Densities and outputs are (n_rhs, sum N_i), instances concatenated.
@@ -250,7 +261,7 @@ def plan_batched(points_list, kappas, p_s=3, p_ang=5, leaf_size=0.25,
     offsets[1:] = np.cumsum([len(p) for p in points_list])
     kap = np.ascontiguousarray(np.asarray(kappas, dtype=np.float64))
     o = _opts(precision, n_rhs, leaf_grid, levels, stages, host_only, device,
-              cone_margin, prop_kernel, lookup)
+              cone_margin, prop_kernel, lookup, autotune)
     h = ctypes.c_void_p()
     _check(load_library().ifgf_plan_batched(
         ctypes.byref(h), len(points_list), offsets.ctypes.data_as(ctypes.c_void_p),

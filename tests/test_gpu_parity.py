@@ -236,3 +236,53 @@ def test_kernel_variants_match_oracle(prop, lookup, precision, tol):
     g, _ = run_gpu(p, a, k, precision=precision, prop_kernel=prop, lookup=lookup)
     o = oracle.ifgf(p, a[0], k, leaf_grid=(2, 4, 8))
     assert relerr(g[0], o) <= tol
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
+def test_graph_replays_match_eager(precision, tol):
+    """The HIP-graph apply, replayed several times with eager work and
+    synchronisations in between, matches the eager apply every time.  (The
+    matrix-core propagation adds octant contributions with LDS atomics, so
+    FP32 results may differ from run to run by rounding.)"""
+    import torch
+    import paper_2112_15198_amd as ifgf
+    n = 9000
+    p = W.spheroid(n)
+    k = W.kappa_oblate_10ppw(n)
+    dt = torch.complex128 if precision == "fp64" else torch.complex64
+    say("graph replay", precision)
+    pl = ifgf.plan(p, k, precision=precision, n_rhs=2, prop_kernel="grouped")
+    a = torch.from_numpy(W.densities(n, 2, 51)).to(dt).cuda()
+    b = torch.from_numpy(W.densities(n, 2, 52)).to(dt).cuda()
+    ref_a = pl.apply(a).cpu().numpy()
+    ref_b = pl.apply(b).cpu().numpy()
+    out = torch.empty_like(a)
+    for rep in range(3):
+        pl.apply(a, out=out, graph=True)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        assert relerr(got, ref_a) <= tol, rep
+        eager_b = pl.apply(b).cpu().numpy()      # eager work between replays
+        assert relerr(eager_b, ref_b) <= tol
+        torch.cuda.synchronize()
+    pl.check()
+    o = oracle.ifgf(p, W.densities(n, 2, 51)[1], k, leaf_grid=(2, 4, 8))
+    assert relerr(got[1], o) <= (1e-10 if precision == "fp64" else 2e-5)
+    pl.close()
+
+
+def test_autotune_picks_a_kernel_per_level_and_stays_exact():
+    import paper_2112_15198_amd as ifgf
+    n = 20000
+    p = W.fibonacci_sphere(n)
+    k = W.kappa_sphere_10ppw(n)
+    a = W.densities(n, 1, 53)
+    say("autotune")
+    g, info = run_gpu(p, a, k, autotune=True)
+    tuned = [l for l in range(1, info["n_steps"]) if info["autotune_ms"][l][0] > 0]
+    assert tuned, info["autotune_ms"]
+    for l in tuned:
+        t_node, t_mfma = info["autotune_ms"][l]
+        assert info["prop_mode"][l] == (2 if t_mfma < t_node else 1)
+    o = oracle.ifgf(p, a[0], k, leaf_grid=(2, 4, 8))
+    assert relerr(g[0], o) <= 1e-10
