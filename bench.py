@@ -53,6 +53,23 @@ def flops_per_eval(P):
     return 4 * P + 8
 
 
+def measured_traffic(stage, workload, precision):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE record (copy-calibrated), or None when
+    there is no record for it or the kernel source changed since."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2112_15198_amd", "csrc", "ifgf_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for f in glob.glob(os.path.join(ROOT, "profiles", "*_traffic.json")):
+        rec = json.load(open(f))
+        if (rec.get("stage") == stage and rec.get("workload") == workload
+                and rec.get("precision") == precision
+                and rec.get("kernel_source_sha256") == sha):
+            return rec["traffic_bytes_per_launch"]
+    return None
+
+
 def time_applies(pl, a, steps, warmup, graph):
     """Mean ms per apply over `steps` applies (after `warmup`), bracketed by
     torch.cuda.synchronize; graph=True replays the captured apply."""
@@ -95,6 +112,9 @@ def main():
     ap.add_argument("--precision", choices=["both", "fp32", "fp64"], default="both")
     ap.add_argument("--samples-batch", type=int, default=256,
                     help="error-check targets per instance of a batched workload")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 256 MiB device-to-device copy three times "
+                         "(known bytes, for calibrating rocprofv3 FETCH/WRITE_SIZE)")
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the CPU oracle (baseline and error check)")
     args = ap.parse_args()
@@ -104,6 +124,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        nel = 64 * 1024 * 1024
+        src = torch.ones(nel, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nel * 4, "copies": 3}), flush=True)
+        return
     import paper_2112_15198_amd as ifgf
     from paper_2112_15198_amd import workloads as W
 
@@ -180,7 +209,8 @@ def main():
     achieved = per_launch / (avg_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[head]
     roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                "traffic": measured_traffic(dom, args.workload, head),
                 "kernel": dom, "launches_per_step": launches,
                 "avg_launch_ms": round(avg_ms, 4),
                 "flop_per_launch": per_launch,
