@@ -567,14 +567,18 @@ prop_mfma_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc
   constexpr int NCOL = CB * MAXR;  // <= 32 columns
   constexpr int NAMAX = 8;         // child cones per octant with a cached slot
   constexpr int NWP = NW + 1;      // weights per node plus a zero slot
-  __shared__ T s_L[8 * P * NWP];          // Lagrange weights of (o, p), then 0
+  __shared__ T s_u[8 * P * 3];            // local coordinates of (o, p)
+  __shared__ T s_L[P * NWP];              // Lagrange weights of one octant, then 0
   __shared__ T s_rat[8 * P * 2];
-  __shared__ int s_alpha[8 * P];          // child cone alpha of (o, p)
   __shared__ int s_dist[8 * P];           // distinct child cones per octant
   __shared__ unsigned char s_rows[8 * P]; // nodes of octant o grouped by alpha
   __shared__ int s_rbeg[8 * (P + 1)];
   __shared__ int s_na[8];
+  // The output accumulators; during set-up the same memory holds the child
+  // cone alpha of every (o, p).
+  static_assert(NCOL * P * 2 * sizeof(T) >= 8 * P * sizeof(int), "alias");
   __shared__ T s_y[NCOL * P * 2];
+  int* const s_alpha = reinterpret_cast<int*>(s_y);
   __shared__ int s_pslot[CB], s_box[CB];
   __shared__ int s_nlist[8 * CB], s_child[8 * CB], s_no[8], s_ipre[9];
   __shared__ int s_cslot[8 * CB * NAMAX];
@@ -627,11 +631,9 @@ prop_mfma_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc
     int ct = cone_index(cr.q[1], S.nt, u1);
     int cp = cone_index(cr.q[2], S.np, u2);
     s_alpha[i] = (cs * S.nt + ct) * S.np + cp;
-    T* L = s_L + i * NWP;
-    lagrange<PS, T>((T)u0, A.cheb.ts, A.cheb.ws, L);
-    lagrange<PA, T>((T)u1, A.cheb.ta, A.cheb.wa, L + PS);
-    lagrange<PA, T>((T)u2, A.cheb.ta, A.cheb.wa, L + PS + PA);
-    L[NW] = 0;
+    s_u[3 * i] = (T)u0;
+    s_u[3 * i + 1] = (T)u1;
+    s_u[3 * i + 2] = (T)u2;
     T gc, gs;
     expi<T>(kappa * (cr.r - rj), gc, gs);
     T amp = (T)(rj / cr.r);
@@ -720,52 +722,71 @@ prop_mfma_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc
       s_cslot[idx] = cs;
     }
     __syncthreads();
-    // Work items over all octants: (octant o, child cone k, N-tile).  The B
-    // fragments (child cone values of 16 (box, rhs) columns) are loaded once
-    // per item and reused for the M-tiles (node rows) of that child cone.
-    // Operand preparation is branch-free so that the loads batch: padded
-    // columns read a valid cone and are scaled by 0, padded K (q >= P)
-    // points at the zero weight slot, padded rows use a 0 factor.
-    const int nitems = s_ipre[8];
-    for (int item = wave; item < nitems; item += NWAVES) {
-      int o = 0;
-      while (s_ipre[o + 1] <= item) ++o;
-      const int ncols = s_no[o] * nrhs;
+    // Octant by octant (all waves on one octant, so every (box, node) of
+    // the output is updated by one lane at a time: plain LDS
+    // read-modify-write), work items (child cone k, M-tile, N-tile).  Operand
+    // preparation is branch-free so that the loads batch: padded columns
+    // read a valid cone and are scaled by 0, padded K (q >= P) points at the
+    // zero weight slot, padded rows use a 0 factor.
+    for (int o = 0; o < 8; ++o) {
+      const int no = s_no[o];
+      if (no == 0) continue;  // uniform across the block
+      const int ncols = no * nrhs;
       const int ntn = (ncols + 15) / 16;
-      const int li = item - s_ipre[o];
-      const int k = li / ntn, nt = li - (li / ntn) * ntn;
-      const int rb0 = s_rbeg[o * (P + 1) + k], rlen = s_rbeg[o * (P + 1) + k + 1] - rb0;
-      const int col = nt * 16 + (lane & 15);
-      const bool colok = col < ncols;
-      const int n = colok ? col / nrhs : 0;
-      const int r = colok ? col - n * nrhs : 0;
-      int cs = -1;
-      if (colok) {
-        if (k < NAMAX) {
-          cs = s_cslot[(o * CB + n) * NAMAX + k];
-        } else {
-          cs = cone_lookup(
-              S, (unsigned long long)s_child[o * CB + n] * S.ngrid + s_dist[o * P + k]);
-          if (cs < 0) atomicOr(A.err, 1);
+      const int na = s_na[o];
+      // Lagrange weights of this octant's nodes (plus the zero slot).
+      for (int p = tid; p < P; p += blockDim.x) {
+        const T* u = s_u + 3 * (o * P + p);
+        T* L = s_L + p * NWP;
+        lagrange<PS, T>(u[0], A.cheb.ts, A.cheb.ws, L);
+        lagrange<PA, T>(u[1], A.cheb.ta, A.cheb.wa, L + PS);
+        lagrange<PA, T>(u[2], A.cheb.ta, A.cheb.wa, L + PS + PA);
+        L[NW] = 0;
+      }
+      __syncthreads();
+      // M-tiles of all child cones of this octant, enumerated in order.
+      int nmt = 0;
+      for (int k = 0; k < na; ++k)
+        nmt += (s_rbeg[o * (P + 1) + k + 1] - s_rbeg[o * (P + 1) + k] + 15) / 16;
+      for (int item = wave; item < nmt * ntn; item += NWAVES) {
+        const int gm = item / ntn, nt = item - (item / ntn) * ntn;
+        int k = 0, mt = gm;
+        for (;;) {
+          const int t = (s_rbeg[o * (P + 1) + k + 1] - s_rbeg[o * (P + 1) + k] + 15) / 16;
+          if (mt < t) break;
+          mt -= t;
+          ++k;
         }
-      }
-      const T bm = cs >= 0 ? (T)1 : (T)0;
-      const CT* vp = Vc + ((int64_t)(cs >= 0 ? cs : 0) * nrhs + (cs >= 0 ? r : 0)) * P;
-      T br[KP / 4], bi[KP / 4];
+        const int rb0 = s_rbeg[o * (P + 1) + k], rlen = s_rbeg[o * (P + 1) + k + 1] - rb0;
+        const int col = nt * 16 + (lane & 15);
+        const bool colok = col < ncols;
+        const int n = colok ? col / nrhs : 0;
+        const int r = colok ? col - n * nrhs : 0;
+        int cs = -1;
+        if (colok) {
+          if (k < NAMAX) {
+            cs = s_cslot[(o * CB + n) * NAMAX + k];
+          } else {
+            cs = cone_lookup(
+                S, (unsigned long long)s_child[o * CB + n] * S.ngrid + s_dist[o * P + k]);
+            if (cs < 0) atomicOr(A.err, 1);
+          }
+        }
+        const T bm = cs >= 0 ? (T)1 : (T)0;
+        const CT* vp = Vc + ((int64_t)(cs >= 0 ? cs : 0) * nrhs + (cs >= 0 ? r : 0)) * P;
+        T br[KP / 4], bi[KP / 4];
 #pragma unroll
-      for (int kk = 0; kk < KP / 4; ++kk) {
-        const int q = min(4 * kk + kq, P - 1);
-        const CT x = vp[q];
-        br[kk] = x.x * bm;
-        bi[kk] = x.y * bm;
-      }
-      const int b = colok ? s_nlist[o * CB + n] : 0;
-      for (int mt = 0; mt * 16 < rlen; ++mt) {
+        for (int kk = 0; kk < KP / 4; ++kk) {
+          const int q = min(4 * kk + kq, P - 1);
+          const CT x = vp[q];
+          br[kk] = x.x * bm;
+          bi[kk] = x.y * bm;
+        }
         // A operand: row m of this tile -> node p; W[p][q] = L_a L_b L_c.
         const int m = mt * 16 + (lane & 15);
         const int pa = m < rlen ? (int)s_rows[o * P + rb0 + m] : 0;
         const T am = m < rlen ? (T)1 : (T)0;
-        const T* L = s_L + (o * P + pa) * NWP;
+        const T* L = s_L + pa * NWP;
         T av[KP / 4];
 #pragma unroll
         for (int kk = 0; kk < KP / 4; ++kk) {
@@ -789,19 +810,20 @@ prop_mfma_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc
           accr = Mfma<T>::mma(av[kk], br[kk], accr);
           acci = Mfma<T>::mma(av[kk], bi[kk], acci);
         }
-        // Rows -> nodes, columns -> (box, rhs); times the ratio.  Octants
-        // run concurrently on different waves: LDS atomic adds.
+        // Rows -> nodes, columns -> (box, rhs); times the ratio.
         if (colok) {
+          const int b = s_nlist[o * CB + n];
 #pragma unroll
           for (int r4 = 0; r4 < 4; ++r4) {
             if (pe[r4] >= 0) {
               T* y = s_y + 2 * ((b * MAXR + r) * P + pe[r4]);
-              atomicAdd(y, accr[r4] * gce[r4] - acci[r4] * gse[r4]);
-              atomicAdd(y + 1, accr[r4] * gse[r4] + acci[r4] * gce[r4]);
+              y[0] += accr[r4] * gce[r4] - acci[r4] * gse[r4];
+              y[1] += accr[r4] * gse[r4] + acci[r4] * gce[r4];
             }
           }
         }
       }
+      __syncthreads();
     }
     __syncthreads();
     // Write the parent cones of this sub-chunk.
