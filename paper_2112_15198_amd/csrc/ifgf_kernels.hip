@@ -566,9 +566,15 @@ prop_mfma_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc
   constexpr int CB = ChunkCols<T, MAXR>::boxes;
   constexpr int NCOL = CB * MAXR;  // <= 32 columns
   constexpr int NAMAX = 8;         // child cones per octant with a cached slot
-  constexpr int NWP = NW + 1;      // weights per node plus a zero slot
+  constexpr int KS = (KP / 4 + 3) / 4 * 4;  // k-steps, padded to whole 4-vectors
+  constexpr int RS = 4 * KS + 4;            // row stride of s_A (bank offset)
+  typedef T T4 __attribute__((ext_vector_type(4)));
   __shared__ T s_u[8 * P * 3];            // local coordinates of (o, p)
-  __shared__ T s_L[P * NWP];              // Lagrange weights of one octant, then 0
+  __shared__ T s_L[P * NW];               // Lagrange weights of one octant
+  // Interpolation matrix of one octant: row pos (the node at position pos
+  // of the octant's grouping by child cone), entry q at [q % 4][q / 4],
+  // zero for q >= P.
+  __shared__ __attribute__((aligned(16))) T s_A[P * RS];
   __shared__ T s_rat[8 * P * 2];
   __shared__ int s_dist[8 * P];           // distinct child cones per octant
   __shared__ unsigned char s_rows[8 * P]; // nodes of octant o grouped by alpha
@@ -582,9 +588,6 @@ prop_mfma_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc
   __shared__ int s_pslot[CB], s_box[CB];
   __shared__ int s_nlist[8 * CB], s_child[8 * CB], s_no[8], s_ipre[9];
   __shared__ int s_cslot[8 * CB * NAMAX];
-  // For q = (a, b, c): the offsets of L_a, L_b, L_c in a node's weights,
-  // packed a | (PS + b) << 8 | (PS + PA + c) << 16; zero weight past P.
-  __shared__ unsigned int s_qidx[KP];
 
   const StepDev& S = A.step[l];
   const StepDev& Q = A.step[l + 1];
@@ -606,10 +609,11 @@ prop_mfma_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc
   const double Hc = S.inst_H[inst];
   const double kappa = A.inst_kappa[inst];
 
-  for (int q = tid; q < KP; q += blockDim.x)
-    s_qidx[q] = q < P ? (unsigned)(q / (PA * PA)) | ((unsigned)(PS + (q / PA) % PA) << 8) |
-                            ((unsigned)(PS + PA + q % PA) << 16)
-                      : (unsigned)NW | ((unsigned)NW << 8) | ((unsigned)NW << 16);
+  // The zero padding of s_A (columns q >= P), written once.
+  for (int i = tid; i < P * (4 * KS - P); i += blockDim.x) {
+    const int pos = i / (4 * KS - P), q = P + i % (4 * KS - P);
+    s_A[pos * RS + (q & 3) * KS + (q >> 2)] = 0;
+  }
   // Node geometry, once per block.
   for (int i = tid; i < 8 * P; i += blockDim.x) {
     const int o = i / P, p = i - (i / P) * P;
@@ -678,9 +682,6 @@ prop_mfma_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc
   __syncthreads();
 
   const int kq = lane >> 4;
-  unsigned qreg[KP / 4];
-#pragma unroll
-  for (int kk = 0; kk < KP / 4; ++kk) qreg[kk] = s_qidx[4 * kk + kq];
   for (int sub = 0; sub * CB < nchunk; ++sub) {
     const int nbk = min(CB, nchunk - sub * CB);
     if (tid < nbk) {
@@ -724,101 +725,127 @@ prop_mfma_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc
     __syncthreads();
     // Octant by octant (all waves on one octant, so every (box, node) of
     // the output is updated by one lane at a time: plain LDS
-    // read-modify-write), work items (child cone k, M-tile, N-tile).  Operand
-    // preparation is branch-free so that the loads batch: padded columns
-    // read a valid cone and are scaled by 0, padded K (q >= P) points at the
-    // zero weight slot, padded rows use a 0 factor.
+    // read-modify-write).  Operands need no masks: a padded column reads a
+    // valid cone and is never stored, a padded row reads a valid row of
+    // s_A and is never stored, and the padded K entries of s_A are 0.
     for (int o = 0; o < 8; ++o) {
       const int no = s_no[o];
       if (no == 0) continue;  // uniform across the block
       const int ncols = no * nrhs;
       const int ntn = (ncols + 15) / 16;
       const int na = s_na[o];
-      // Lagrange weights of this octant's nodes (plus the zero slot).
-      for (int p = tid; p < P; p += blockDim.x) {
+      // Lagrange weights of this octant's nodes, in grouped order.
+      for (int pos = tid; pos < P; pos += blockDim.x) {
+        const int p = s_rows[o * P + pos];
         const T* u = s_u + 3 * (o * P + p);
-        T* L = s_L + p * NWP;
+        T* L = s_L + pos * NW;
         lagrange<PS, T>(u[0], A.cheb.ts, A.cheb.ws, L);
         lagrange<PA, T>(u[1], A.cheb.ta, A.cheb.wa, L + PS);
         lagrange<PA, T>(u[2], A.cheb.ta, A.cheb.wa, L + PS + PA);
-        L[NW] = 0;
       }
       __syncthreads();
+      // W[p][q] = L_a L_b L_c for q = (a, b, c): one (pos, a, b) per thread.
+      for (int i = tid; i < P * PS * PA; i += blockDim.x) {
+        const int pos = i / (PS * PA), ab = i - (i / (PS * PA)) * (PS * PA);
+        const int a = ab / PA, bq = ab - (ab / PA) * PA;
+        const T* L = s_L + pos * NW;
+        const T lab = L[a] * L[PS + bq];
+        T* Ar = s_A + pos * RS;
+#pragma unroll
+        for (int cq = 0; cq < PA; ++cq) {
+          const int q = (a * PA + bq) * PA + cq;
+          Ar[(q & 3) * KS + (q >> 2)] = lab * L[PS + PA + cq];
+        }
+      }
+      __syncthreads();
+#ifdef IFGF_BREUSE
+      // Work items (child cone k, N-tile): the B tile is loaded once and
+      // used for every M-tile of k.
+      for (int item = wave; item < na * ntn; item += NWAVES) {
+        const int k = item / ntn, nt = item - (item / ntn) * ntn;
+#else
       // M-tiles of all child cones of this octant, enumerated in order.
       int nmt = 0;
       for (int k = 0; k < na; ++k)
         nmt += (s_rbeg[o * (P + 1) + k + 1] - s_rbeg[o * (P + 1) + k] + 15) / 16;
+      // Work items (child cone k, M-tile, N-tile).
       for (int item = wave; item < nmt * ntn; item += NWAVES) {
         const int gm = item / ntn, nt = item - (item / ntn) * ntn;
-        int k = 0, mt = gm;
+        int k = 0, mt0 = gm;
         for (;;) {
           const int t = (s_rbeg[o * (P + 1) + k + 1] - s_rbeg[o * (P + 1) + k] + 15) / 16;
-          if (mt < t) break;
-          mt -= t;
+          if (mt0 < t) break;
+          mt0 -= t;
           ++k;
         }
+#endif
         const int rb0 = s_rbeg[o * (P + 1) + k], rlen = s_rbeg[o * (P + 1) + k + 1] - rb0;
         const int col = nt * 16 + (lane & 15);
         const bool colok = col < ncols;
         const int n = colok ? col / nrhs : 0;
         const int r = colok ? col - n * nrhs : 0;
-        int cs = -1;
-        if (colok) {
-          if (k < NAMAX) {
-            cs = s_cslot[(o * CB + n) * NAMAX + k];
-          } else {
-            cs = cone_lookup(
-                S, (unsigned long long)s_child[o * CB + n] * S.ngrid + s_dist[o * P + k]);
-            if (cs < 0) atomicOr(A.err, 1);
-          }
+        int cs;
+        if (k < NAMAX) {
+          cs = s_cslot[(o * CB + n) * NAMAX + k];
+        } else {
+          cs = cone_lookup(
+              S, (unsigned long long)s_child[o * CB + n] * S.ngrid + s_dist[o * P + k]);
+          if (cs < 0) atomicOr(A.err, 1);
         }
-        const T bm = cs >= 0 ? (T)1 : (T)0;
-        const CT* vp = Vc + ((int64_t)(cs >= 0 ? cs : 0) * nrhs + (cs >= 0 ? r : 0)) * P;
+        // B operand: lane holds X[4 kk + kq][col].
+        const CT* vp = Vc + ((int64_t)(cs >= 0 ? cs : 0) * nrhs + r) * P + kq;
         T br[KP / 4], bi[KP / 4];
 #pragma unroll
         for (int kk = 0; kk < KP / 4; ++kk) {
-          const int q = min(4 * kk + kq, P - 1);
-          const CT x = vp[q];
-          br[kk] = x.x * bm;
-          bi[kk] = x.y * bm;
+          const CT x = (4 * kk + 3 < P) ? vp[4 * kk] : vp[min(4 * kk, P - 1 - kq)];
+          br[kk] = x.x;
+          bi[kk] = x.y;
         }
-        // A operand: row m of this tile -> node p; W[p][q] = L_a L_b L_c.
-        const int m = mt * 16 + (lane & 15);
-        const int pa = m < rlen ? (int)s_rows[o * P + rb0 + m] : 0;
-        const T am = m < rlen ? (T)1 : (T)0;
-        const T* L = s_L + pa * NWP;
-        T av[KP / 4];
+        const int b = s_nlist[o * CB + n];
+#ifdef IFGF_BREUSE
+        for (int mt = 0; mt * 16 < rlen; ++mt) {
+#else
+        {
+          const int mt = mt0;
+#endif
+          // A operand: lane holds W[row 16 mt + lane % 16][4 kk + kq].
+          const int arow = min(rb0 + mt * 16 + (lane & 15), P - 1);
+          const T4* ap = reinterpret_cast<const T4*>(s_A + arow * RS + kq * KS);
+          T av[KS];
 #pragma unroll
-        for (int kk = 0; kk < KP / 4; ++kk) {
-          const unsigned qi = qreg[kk];
-          av[kk] = L[qi & 0xff] * L[(qi >> 8) & 0xff] * L[qi >> 16] * am;
-        }
-        // Epilogue operands, fetched before the products.
-        int pe[4];
-        T gce[4], gse[4];
-#pragma unroll
-        for (int r4 = 0; r4 < 4; ++r4) {
-          const int mm = mt * 16 + Mfma<T>::row(lane, r4);
-          pe[r4] = mm < rlen ? (int)s_rows[o * P + rb0 + mm] : -1;
-          const int pp = pe[r4] >= 0 ? pe[r4] : 0;
-          gce[r4] = s_rat[2 * (o * P + pp)];
-          gse[r4] = s_rat[2 * (o * P + pp) + 1];
-        }
-        V4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
-#pragma unroll
-        for (int kk = 0; kk < KP / 4; ++kk) {
-          accr = Mfma<T>::mma(av[kk], br[kk], accr);
-          acci = Mfma<T>::mma(av[kk], bi[kk], acci);
-        }
-        // Rows -> nodes, columns -> (box, rhs); times the ratio.
-        if (colok) {
-          const int b = s_nlist[o * CB + n];
+          for (int j = 0; j < KS / 4; ++j) {
+            const T4 v = ap[j];
+            av[4 * j] = v.x;
+            av[4 * j + 1] = v.y;
+            av[4 * j + 2] = v.z;
+            av[4 * j + 3] = v.w;
+          }
+          // Epilogue operands, fetched before the products.
+          int pe[4];
+          T gce[4], gse[4];
 #pragma unroll
           for (int r4 = 0; r4 < 4; ++r4) {
-            if (pe[r4] >= 0) {
-              T* y = s_y + 2 * ((b * MAXR + r) * P + pe[r4]);
-              y[0] += accr[r4] * gce[r4] - acci[r4] * gse[r4];
-              y[1] += accr[r4] * gse[r4] + acci[r4] * gce[r4];
+            const int mm = mt * 16 + Mfma<T>::row(lane, r4);
+            pe[r4] = mm < rlen ? (int)s_rows[o * P + rb0 + mm] : -1;
+            const int pp = pe[r4] >= 0 ? pe[r4] : 0;
+            gce[r4] = s_rat[2 * (o * P + pp)];
+            gse[r4] = s_rat[2 * (o * P + pp) + 1];
+          }
+          V4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+#pragma unroll
+          for (int kk = 0; kk < KP / 4; ++kk) {
+            accr = Mfma<T>::mma(av[kk], br[kk], accr);
+            acci = Mfma<T>::mma(av[kk], bi[kk], acci);
+          }
+          // Rows -> nodes, columns -> (box, rhs); times the ratio.
+          if (colok) {
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) {
+              if (pe[r4] >= 0) {
+                T* y = s_y + 2 * ((b * MAXR + r) * P + pe[r4]);
+                y[0] += accr[r4] * gce[r4] - acci[r4] * gse[r4];
+                y[1] += accr[r4] * gse[r4] + acci[r4] * gce[r4];
+              }
             }
           }
         }
@@ -835,6 +862,408 @@ prop_mfma_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc
       v.x = s_y[2 * ((b * MAXR + r) * P + p)];
       v.y = s_y[2 * ((b * MAXR + r) * P + p) + 1];
       Vp[((int64_t)s_pslot[b] * nrhs + r) * P + p] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// FP32 propagation on the matrix cores, large blocks.  A block of 8 waves
+// takes one chunk of parent cones sharing (instance, gamma') and works
+// through it in sub-chunks of CB boxes.  The node geometry and the Lagrange
+// weights of all eight octants are computed once per block.  Per sub-chunk,
+// octant by octant: the interpolation matrix W of the octant is formed in
+// LDS (rows in the octant's grouping of nodes by child cone), then every
+// wave runs work items (child cone k, M-tile, N-tile) of
+//     C[p][(box, rhs)] = sum_q W[p][q] X[q][(box, rhs)]
+// on 16x16x4 MFMA tiles, the columns being all boxes of the sub-chunk with
+// a child in the octant, and accumulates ratio(p) * C in LDS.  Each wave
+// keeps the B tile of its next item in flight while it computes the
+// current one; the child cone slots of the next octant are looked up
+// during the current octant's items.
+template <int PS, int PA, int MAXR>
+struct BigProp {
+  static constexpr int P = PS * PA * PA;
+  static constexpr int NW = PS + 2 * PA;
+  static constexpr int NK = (P + 3) / 4;          // k-steps of 4
+  static constexpr int KS = (NK + 3) / 4 * 4;     // k-steps padded to whole 4-vectors
+  static constexpr int RS = 4 * KS + 4;           // row stride of the W matrix (bank offset)
+  static constexpr int NWV = 8;
+  static constexpr int CB = 128 / MAXR;           // boxes per sub-chunk
+  static constexpr int NCOL = CB * MAXR;          // <= 128 columns
+  static constexpr int NAMAX = 8;                 // child cones per octant with a cached slot
+  // K order: k-steps 2m and 2m + 1 give lane group kq the adjacent nodes
+  // q = 8m + 2kq and 8m + 2kq + 1 (one 16-byte load of two complex
+  // values); an odd last k-step gives it q = 8 NPAIR + kq.
+  static constexpr int NPAIR = NK / 2;
+  static __device__ __forceinline__ int kstep(int q) {
+    return q < 8 * NPAIR ? 2 * (q >> 3) + (q & 1) : NK - 1;
+  }
+  static __device__ __forceinline__ int kgroup(int q) {
+    return q < 8 * NPAIR ? (q & 7) >> 1 : q - 8 * NPAIR;
+  }
+};
+
+// Decodes work item `item` of octant o (M-tiles of all child cones in
+// order, times N-tiles) into child cone k, row range and tile indices.
+template <int P>
+__device__ __forceinline__ void big_item(const int* rbeg, int item, int ntn, int& k, int& mt,
+                                         int& nt) {
+  const int gm = item / ntn;
+  nt = item - gm * ntn;
+  k = 0;
+  mt = gm;
+  for (;;) {
+    const int t = (rbeg[k + 1] - rbeg[k] + 15) / 16;
+    if (mt < t) break;
+    mt -= t;
+    ++k;
+  }
+}
+
+template <int PS, int PA, int MAXR>
+__device__ __forceinline__ void big_load_b(const StepDev& S, const float2* __restrict__ Vc,
+                                           int* err, const int* cs_tab, const int* ch_tab,
+                                           const int* dist, const int* rbeg, int item, int ntn,
+                                           int ncols, int nrhs, int lane, float* br, float* bi) {
+  typedef BigProp<PS, PA, MAXR> B;
+  constexpr int P = B::P;
+  int k, mt, nt;
+  big_item<P>(rbeg, item, ntn, k, mt, nt);
+  const int col = nt * 16 + (lane & 15), kq = lane >> 4;
+  const int n0 = col / nrhs;
+  const int n = col < ncols ? n0 : 0;
+  const int r = col < ncols ? col - n0 * nrhs : 0;
+  int cs;
+  if (k < B::NAMAX) {
+    cs = cs_tab[n * B::NAMAX + k];
+  } else {
+    cs = cone_lookup(S, (unsigned long long)ch_tab[n] * S.ngrid + dist[k]);
+    if (cs < 0) atomicOr(err, 1);
+  }
+  const float2* vp = Vc + ((int64_t)(cs >= 0 ? cs : 0) * nrhs + r) * P;
+  typedef float v4u __attribute__((ext_vector_type(4), aligned(8)));
+#pragma unroll
+  for (int m = 0; m < B::NPAIR; ++m) {
+    if (8 * m + 7 < P) {
+      const v4u x = *reinterpret_cast<const v4u*>(vp + 8 * m + 2 * kq);
+      br[2 * m] = x.x;
+      bi[2 * m] = x.y;
+      br[2 * m + 1] = x.z;
+      bi[2 * m + 1] = x.w;
+    } else {
+      const float2 x0 = vp[min(8 * m + 2 * kq, P - 1)];
+      const float2 x1 = vp[min(8 * m + 2 * kq + 1, P - 1)];
+      br[2 * m] = x0.x;
+      bi[2 * m] = x0.y;
+      br[2 * m + 1] = x1.x;
+      bi[2 * m + 1] = x1.y;
+    }
+  }
+  if constexpr (B::NK & 1) {
+    const float2 x = vp[min(8 * B::NPAIR + kq, P - 1)];
+    br[B::NK - 1] = x.x;
+    bi[B::NK - 1] = x.y;
+  }
+}
+
+template <int PS, int PA, int MAXR>
+__device__ __forceinline__ void big_compute(const float* s_A, const float* rat,
+                                            const unsigned char* rows, const int* rbeg,
+                                            const unsigned char* nl, float* s_y, int item, int ntn,
+                                            int ncols, int nrhs, int lane, const float* br,
+                                            const float* bi) {
+  typedef BigProp<PS, PA, MAXR> B;
+  constexpr int P = B::P;
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  int k, mt, nt;
+  big_item<P>(rbeg, item, ntn, k, mt, nt);
+  const int rb0 = rbeg[k], rlen = rbeg[k + 1] - rb0;
+  const int col = nt * 16 + (lane & 15), kq = lane >> 4;
+  const bool colok = col < ncols;
+  const int n0 = col / nrhs;
+  const int r = col - n0 * nrhs;
+  const int yb = colok ? ((int)nl[n0] * MAXR + r) * P : 0;
+  // A operand: lane holds W[row 16 mt + lane % 16][q] with q the node of
+  // k-step kk for lane group kq.
+  const int arow = min(rb0 + mt * 16 + (lane & 15), P - 1);
+  const v4* ap = reinterpret_cast<const v4*>(s_A + arow * B::RS + kq * B::KS);
+  float av[B::KS];
+#pragma unroll
+  for (int j = 0; j < B::KS / 4; ++j) {
+    const v4 v = ap[j];
+    av[4 * j] = v.x;
+    av[4 * j + 1] = v.y;
+    av[4 * j + 2] = v.z;
+    av[4 * j + 3] = v.w;
+  }
+  int pe[4];
+  float gc[4], gs[4];
+#pragma unroll
+  for (int r4 = 0; r4 < 4; ++r4) {
+    const int mm = mt * 16 + 4 * (lane >> 4) + r4;
+    const int pos = rb0 + (mm < rlen ? mm : 0);
+    pe[r4] = mm < rlen ? (int)rows[pos] : -1;
+    gc[r4] = rat[2 * pos];
+    gs[r4] = rat[2 * pos + 1];
+  }
+  v4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+#pragma unroll
+  for (int kk = 0; kk < B::NK; ++kk) {
+    accr = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kk], br[kk], accr, 0, 0, 0);
+    acci = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kk], bi[kk], acci, 0, 0, 0);
+  }
+  if (colok) {
+#pragma unroll
+    for (int r4 = 0; r4 < 4; ++r4) {
+      if (pe[r4] >= 0) {
+        float* yy = s_y + 2 * (yb + pe[r4]);
+        yy[0] += accr[r4] * gc[r4] - acci[r4] * gs[r4];
+        yy[1] += accr[r4] * gs[r4] + acci[r4] * gc[r4];
+      }
+    }
+  }
+}
+
+template <int PS, int PA, int MAXR>
+__global__ void __launch_bounds__(512)
+prop_big_kernel(ApplyArgs A, int l, const float2* __restrict__ Vc, float2* __restrict__ Vp) {
+  typedef BigProp<PS, PA, MAXR> B;
+  constexpr int P = B::P, NW = B::NW, KS = B::KS, RS = B::RS, CB = B::CB, NAMAX = B::NAMAX;
+  constexpr int NWV = B::NWV;
+  static_assert(P <= 128, "two nodes per lane");
+  __shared__ float s_L[8 * P * NW];                  // weights of (o, pos)
+  __shared__ __attribute__((aligned(16))) float s_A[P * RS];
+  __shared__ float s_rat[8 * P * 2];                 // ratio of (o, pos)
+  __shared__ unsigned char s_rows[8 * P];            // node p at (o, pos)
+  __shared__ int s_rbeg[8 * (P + 1)];
+  __shared__ int s_dist[8 * P];
+  __shared__ int s_na[8];
+  // Accumulators of a sub-chunk; during the set-up the same memory holds
+  // the child cone alpha, local coordinates u and ratio of every (o, p).
+  __shared__ float s_y[B::NCOL * P * 2];
+  static_assert(B::NCOL * P * 2 >= 8 * P * 6, "set-up scratch");
+  int* const s_alpha = reinterpret_cast<int*>(s_y);
+  float* const s_u = s_y + 8 * P;
+  float* const s_ratp = s_y + 8 * P * 4;
+  __shared__ int s_pslot[CB], s_box[CB];
+  __shared__ int s_child[8][CB];                     // children per octant, compacted
+  __shared__ unsigned char s_nl[8][CB];              // their box index in the sub-chunk
+  __shared__ int s_no[8];
+  __shared__ int s_cs[2][CB * NAMAX];                // child cone slots, two octants
+
+  const StepDev& S = A.step[l];
+  const StepDev& Q = A.step[l + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nrhs = A.nrhs;
+  const int64_t c = blockIdx.x;
+  const int64_t g0 = Q.chunk_start[c];
+  const int nchunk = Q.chunk_len[c];
+  const unsigned long long key0 = Q.cone_key[Q.gslot[g0]];
+  const int64_t j0 = (int64_t)(key0 / (unsigned long long)Q.ngrid);
+  const int64_t g = (int64_t)(key0 - (unsigned long long)j0 * Q.ngrid);
+  const int is = (int)(g / ((int64_t)Q.nt * Q.np));
+  const int it = (int)((g / Q.np) % Q.nt);
+  const int ip = (int)(g % Q.np);
+  const int inst = Q.inst[j0];
+  const double hp = Q.inst_h[inst];
+  const double hc = S.inst_h[inst];
+  const double Hc = S.inst_H[inst];
+  const double kappa = A.inst_kappa[inst];
+
+  // Node geometry of (o, p), as in prop_mfma_kernel.
+  for (int i = tid; i < 8 * P; i += blockDim.x) {
+    const int o = i / P, p = i - (i / P) * P;
+    const int a = p / (PA * PA), bb = (p / PA) % PA, cc = p % PA;
+    double yp[3];
+    node_offset<PS, PA>(Q, hp, is, it, ip, a, bb, cc, yp);
+    double y0, y1, y2, rj;
+    {
+      IFGF_NO_CONTRACT
+      y0 = yp[0] - (((o >> 2) & 1) ? 0.5 * Hc : -0.5 * Hc);
+      y1 = yp[1] - (((o >> 1) & 1) ? 0.5 * Hc : -0.5 * Hc);
+      y2 = yp[2] - ((o & 1) ? 0.5 * Hc : -0.5 * Hc);
+      rj = sqrt(yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]);
+    }
+    ConeCoord cr = cone_coord(S, hc, y0, y1, y2);
+    double u0, u1, u2;
+    int cs = cone_index(cr.q[0], S.ns, u0);
+    int ct = cone_index(cr.q[1], S.nt, u1);
+    int cp = cone_index(cr.q[2], S.np, u2);
+    s_alpha[i] = (cs * S.nt + ct) * S.np + cp;
+    s_u[3 * i] = (float)u0;
+    s_u[3 * i + 1] = (float)u1;
+    s_u[3 * i + 2] = (float)u2;
+    float gcv, gsv;
+    expi<float>(kappa * (cr.r - rj), gcv, gsv);
+    const float amp = (float)(rj / cr.r);
+    s_ratp[2 * i] = gcv * amp;
+    s_ratp[2 * i + 1] = gsv * amp;
+  }
+  // Zero the W matrix once: its padding (nodes q >= P, k-steps >= NK) is
+  // never written again.
+  for (int i = tid; i < P * RS; i += blockDim.x) s_A[i] = 0.f;
+  __syncthreads();
+  // Distinct child cones of octant o = wave and its nodes grouped by child
+  // cone, with wave ballots; lane holds nodes lane and lane + 64.
+  {
+    const int o = wave;
+    const bool has0 = lane < P, has1 = lane + 64 < P;
+    const int a0 = has0 ? s_alpha[o * P + lane] : -1;
+    const int a1 = has1 ? s_alpha[o * P + lane + 64] : -1;
+    bool f0 = has0, f1 = has1;
+    int k0 = 0, k1 = 0, na = 0;
+    for (;;) {
+      const unsigned long long m0 = __ballot(f0), m1 = __ballot(f1);
+      if (m0 == 0ull && m1 == 0ull) break;
+      const int lead = m0 ? __shfl(a0, __ffsll((long long)m0) - 1)
+                          : __shfl(a1, __ffsll((long long)m1) - 1);
+      if (f0 && a0 == lead) { k0 = na; f0 = false; }
+      if (f1 && a1 == lead) { k1 = na; f1 = false; }
+      if (lane == 0) s_dist[o * P + na] = lead;
+      ++na;
+    }
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    int base = 0;
+    for (int k = 0; k < na; ++k) {
+      const unsigned long long m0 = __ballot(has0 && k0 == k), m1 = __ballot(has1 && k1 == k);
+      if (has0 && k0 == k) s_rows[o * P + base + __popcll(m0 & lt)] = (unsigned char)lane;
+      if (has1 && k1 == k)
+        s_rows[o * P + base + __popcll(m0) + __popcll(m1 & lt)] = (unsigned char)(lane + 64);
+      if (lane == 0) s_rbeg[o * (P + 1) + k] = base;
+      base += __popcll(m0) + __popcll(m1);
+    }
+    if (lane == 0) {
+      s_rbeg[o * (P + 1) + na] = base;
+      s_na[o] = na;
+    }
+  }
+  __syncthreads();
+  // Lagrange weights and ratios in grouped order.
+  for (int i = tid; i < 8 * P; i += blockDim.x) {
+    const int o = i / P;
+    const int p = s_rows[i];
+    const float* u = s_u + 3 * (o * P + p);
+    float* L = s_L + i * NW;
+    lagrange<PS, float>(u[0], A.cheb.ts, A.cheb.ws, L);
+    lagrange<PA, float>(u[1], A.cheb.ta, A.cheb.wa, L + PS);
+    lagrange<PA, float>(u[2], A.cheb.ta, A.cheb.wa, L + PS + PA);
+    s_rat[2 * i] = s_ratp[2 * (o * P + p)];
+    s_rat[2 * i + 1] = s_ratp[2 * (o * P + p) + 1];
+  }
+  __syncthreads();
+
+  for (int sub = 0; sub * CB < nchunk; ++sub) {
+    const int nbk = min(CB, nchunk - sub * CB);
+    if (tid < nbk) {
+      const int ps = Q.gslot[g0 + (int64_t)sub * CB + tid];
+      s_pslot[tid] = ps;
+      s_box[tid] = (int)(Q.cone_key[ps] / (unsigned long long)Q.ngrid);
+    }
+    for (int i = tid; i < B::NCOL * P * 2; i += blockDim.x) s_y[i] = 0.f;
+    __syncthreads();
+    // Children of the sub-chunk's boxes in octant o = wave, compacted.
+    {
+      const int o = wave;
+      const unsigned long long lt = (1ull << lane) - 1ull;
+      int base = 0;
+      for (int n0 = 0; n0 < nbk; n0 += 64) {
+        const int n = n0 + lane;
+        const int kc = n < nbk ? Q.child[8 * (int64_t)s_box[n] + o] : -1;
+        const unsigned long long m = __ballot(kc >= 0);
+        if (kc >= 0) {
+          const int pos = base + __popcll(m & lt);
+          s_child[o][pos] = kc;
+          s_nl[o][pos] = (unsigned char)n;
+        }
+        base += __popcll(m);
+      }
+      if (lane == 0) s_no[o] = base;
+    }
+    __syncthreads();
+    // Child cone slots of octant o into buffer bf.  The octants with
+    // children alternate between the two buffers.
+    auto lookup = [&](int o, int bf) {
+      const int no = s_no[o], na = min(s_na[o], NAMAX);
+      for (int i = tid; i < no * na; i += blockDim.x) {
+        const int k = i / no, n = i - k * no;
+        const int cs = cone_lookup(S, (unsigned long long)s_child[o][n] * S.ngrid +
+                                          s_dist[o * P + k]);
+        if (cs < 0) atomicOr(A.err, 1);
+        s_cs[bf][n * NAMAX + k] = cs;
+      }
+    };
+    int buf = 0;
+    {
+      int of = 0;
+      while (of < 8 && s_no[of] == 0) ++of;
+      if (of < 8) lookup(of, 0);
+    }
+    for (int o = 0; o < 8; ++o) {
+      const int no = s_no[o];
+      if (no == 0) continue;  // uniform across the block
+      const int ncols = no * nrhs;
+      const int ntn = (ncols + 15) / 16;
+      // W of octant o: one (pos, a, b) per thread, five entries each.
+      for (int i = tid; i < P * PS * PA; i += blockDim.x) {
+        const int pos = i / (PS * PA), ab = i - (i / (PS * PA)) * (PS * PA);
+        const int a = ab / PA, bq = ab - (ab / PA) * PA;
+        const float* L = s_L + (o * P + pos) * NW;
+        const float lab = L[a] * L[PS + bq];
+        float* Ar = s_A + pos * RS;
+#pragma unroll
+        for (int cq = 0; cq < PA; ++cq) {
+          const int q = (a * PA + bq) * PA + cq;
+          Ar[B::kgroup(q) * KS + B::kstep(q)] = lab * L[PS + PA + cq];
+        }
+      }
+      // The next octant's slots, into the buffer the previous octant read.
+      {
+        int o1 = o + 1;
+        while (o1 < 8 && s_no[o1] == 0) ++o1;
+        if (o1 < 8) lookup(o1, buf ^ 1);
+      }
+      __syncthreads();
+      const int* rbeg = s_rbeg + o * (P + 1);
+      int nmt = 0;
+      for (int k = 0; k < s_na[o]; ++k) nmt += (rbeg[k + 1] - rbeg[k] + 15) / 16;
+      const int nitem = nmt * ntn;
+      if (wave < nitem) {
+        float br0[B::NK], bi0[B::NK], br1[B::NK], bi1[B::NK];
+#define IFGF_BIG_LOAD(IT, BR, BI)                                                           \
+  big_load_b<PS, PA, MAXR>(S, Vc, A.err, s_cs[buf], s_child[o], s_dist + o * P, rbeg, IT, ntn,  \
+                           ncols, nrhs, lane, BR, BI)
+#define IFGF_BIG_COMP(IT, BR, BI)                                                         \
+  big_compute<PS, PA, MAXR>(s_A, s_rat + 2 * o * P, s_rows + o * P, rbeg, s_nl[o], s_y, IT, \
+                            ntn, ncols, nrhs, lane, BR, BI)
+        int item = wave;
+        IFGF_BIG_LOAD(item, br0, bi0);
+        for (;;) {
+          const int i1 = item + NWV < nitem ? item + NWV : item;
+          IFGF_BIG_LOAD(i1, br1, bi1);
+          IFGF_BIG_COMP(item, br0, bi0);
+          if (i1 == item) break;
+          item = i1;
+          const int i2 = item + NWV < nitem ? item + NWV : item;
+          IFGF_BIG_LOAD(i2, br0, bi0);
+          IFGF_BIG_COMP(item, br1, bi1);
+          if (i2 == item) break;
+          item = i2;
+        }
+#undef IFGF_BIG_LOAD
+#undef IFGF_BIG_COMP
+      }
+      buf ^= 1;
+      __syncthreads();
+    }
+    // Write the parent cones of this sub-chunk.
+    for (int idx = tid; idx < nbk * nrhs * P; idx += blockDim.x) {
+      const int bx = idx / (nrhs * P);
+      const int rem = idx - bx * (nrhs * P);
+      const int r = rem / P, p = rem - (rem / P) * P;
+      float2 v;
+      v.x = s_y[2 * ((bx * MAXR + r) * P + p)];
+      v.y = s_y[2 * ((bx * MAXR + r) * P + p) + 1];
+      Vp[((int64_t)s_pslot[bx] * nrhs + r) * P + p] = v;
     }
     __syncthreads();
   }
@@ -1110,6 +1539,19 @@ int chunk_boxes(int precision, int nrhs) {
          (precision == 0 ? ChunkCols<double, 1>::boxes : ChunkCols<float, 1>::boxes) / maxr;
 }
 
+// The grouped (matrix-core) propagation of one level: 512-thread blocks in
+// FP32, 256-thread blocks in FP64 (whose operands do not fit the former's
+// LDS layout).
+template <int PS, int PA, typename T, int MAXR>
+static void launch_grouped(const ApplyArgs& A, int l, const typename C2<T>::type* Vc,
+                           typename C2<T>::type* Vp, int64_t nchunks, hipStream_t st) {
+  if constexpr (sizeof(T) == 4) {
+    prop_big_kernel<PS, PA, MAXR><<<(unsigned)nchunks, 512, 0, st>>>(A, l, Vc, Vp);
+  } else {
+    prop_mfma_kernel<PS, PA, T, MAXR><<<(unsigned)nchunks, kMfmaThreads, 0, st>>>(A, l, Vc, Vp);
+  }
+}
+
 template <int PS, int PA, typename T, int MAXR>
 static hipError_t apply_impl(const ApplyArgs& A, const void* dens_user,
                              void* out_user, hipStream_t st, Profiler* prof) {
@@ -1140,8 +1582,7 @@ static hipError_t apply_impl(const ApplyArgs& A, const void* dens_user,
         bool done = false;
         if constexpr (P <= kMfmaMaxP) {
           if (Qh.prop_grouped) {
-            IFGF_TIMED(6, (prop_mfma_kernel<PS, PA, T, MAXR>
-                           <<<(unsigned)Qh.nchunks, kMfmaThreads, 0, st>>>(A, l, Vcur, Vnext)));
+            IFGF_TIMED(6, (launch_grouped<PS, PA, T, MAXR>(A, l, Vcur, Vnext, Qh.nchunks, st)));
             done = true;
           }
         }
@@ -1170,7 +1611,7 @@ static hipError_t prop_level_impl(const ApplyArgs& A, int l, bool grouped,
   if (Qh.ncones <= 0) return hipSuccess;
   if constexpr (P <= kMfmaMaxP) {
     if (grouped && Qh.nchunks > 0) {
-      prop_mfma_kernel<PS, PA, T, MAXR><<<(unsigned)Qh.nchunks, kMfmaThreads, 0, st>>>(A, l, Vc, Vp);
+      launch_grouped<PS, PA, T, MAXR>(A, l, Vc, Vp, Qh.nchunks, st);
       return hipGetLastError();
     }
   }
