@@ -67,17 +67,18 @@ typedef struct ifgf_opts {
                        called on such a plan */
   int device;       /* HIP device ordinal; -1 uses the current device */
   void* stream;     /* hipStream_t used by ifgf_apply; NULL = null stream */
-  int prop_kernel;  /* propagation kernel per level: 0 chooses by the number
-                       of boxes sharing each parent cone index (grouped
-                       matrix-core form when >= 32 on average, per-node form
-                       otherwise), 1 forces the per-node form, 2 the grouped
+  int prop_kernel;  /* propagation kernel per level: 0 chooses by the mean
+                       number of boxes sharing a parent cone index (>= 32:
+                       matrix-core blocks; >= 4: one-wave matrix-core tasks;
+                       else per-node), 1 forces the per-node form, 2 the
+                       matrix-core block form, 3 the one-wave matrix-core
                        form */
   int lookup;       /* cone look-up: 0 dense tables where a level's table
                        (boxes x cone grid) has <= 2^28 entries, hash tables
                        elsewhere; 1 hash tables everywhere */
-  int autotune;     /* 1: at plan time, time both propagation kernels on
-                       every level where both apply and keep the faster
-                       (overrides prop_kernel there) */
+  int autotune;     /* 1: at plan time, time the three propagation kernels
+                       on every level where the matrix-core forms apply and
+                       keep the fastest (overrides prop_kernel there) */
   double cone_margin; /* a point within cone_margin cone widths of a cone
                        boundary also marks the adjacent cone relevant, so
                        that look-ups along other rounding paths never miss;
@@ -102,10 +103,12 @@ typedef struct ifgf_info {
                                          evaluations of Propagation into
                                          step l (l >= 1) */
   int prop_mode[IFGF_MAX_LEVELS];      /* kernel of Propagation into step l:
-                                         1 per-node, 2 matrix-core */
-  float autotune_ms[IFGF_MAX_LEVELS][2]; /* autotuner timings of Propagation
+                                         1 per-node, 2 matrix-core blocks,
+                                         3 one-wave matrix-core tasks */
+  float autotune_ms[IFGF_MAX_LEVELS][3]; /* autotuner timings of Propagation
                                          into step l: per-node, matrix-core
-                                         (0 when not tuned) */
+                                         blocks, one-wave matrix-core (0 when
+                                         not tuned) */
   int64_t leaf_pairs;     /* (leaf-cone node, source) evaluations of
                              LevelDEvaluations */
   int64_t near_pairs;     /* (target, source) near-field pairs, self included */

@@ -118,7 +118,7 @@ static ifgf_status validate(int p_s, int p_ang, const ifgf_opts& o) {
       return fail(IFGF_EINVAL, "leaf_grid entries must be in [1, 4096]");
   if (o.levels != 0 && o.levels < 3) return fail(IFGF_EINVAL, "levels must be 0 or >= 3");
   if (o.stages < 0 || o.stages > 3) return fail(IFGF_EINVAL, "stages must be in [0, 3]");
-  if (o.prop_kernel < 0 || o.prop_kernel > 2) return fail(IFGF_EINVAL, "prop_kernel must be 0, 1 or 2");
+  if (o.prop_kernel < 0 || o.prop_kernel > 3) return fail(IFGF_EINVAL, "prop_kernel must be 0, 1, 2 or 3");
   if (o.lookup < 0 || o.lookup > 1) return fail(IFGF_EINVAL, "lookup must be 0 or 1");
   if (!(o.cone_margin >= 0.0 && o.cone_margin < 0.25))
     return fail(IFGF_EINVAL, "cone_margin must be in [0, 0.25)");
@@ -151,9 +151,9 @@ static void cheb_nodes(int n, double* t, double* w) {
   }
 }
 
-// Time both propagation kernels on every level where both apply (zeroed
-// cone values: the kernels' work does not depend on the values) and keep
-// the faster one.
+// Time the three propagation kernels on every level where the matrix-core
+// forms apply (zeroed cone values: the kernels' work does not depend on the
+// values) and keep the fastest.
 static void autotune(ifgf_plan_s* P) {
   ApplyArgs& A = P->A;
   hipStream_t st = P->stream;
@@ -170,19 +170,20 @@ static void autotune(ifgf_plan_s* P) {
   for (int l = 0; l + 1 < A.n_steps; ++l) {
     StepDev& Q = P->steps_h[l + 1];
     if (Q.ncones == 0 || Q.nchunks == 0) continue;
-    float best[2] = {0, 0};
-    for (int g = 0; g < 2; ++g) {
-      HIP_TRY(launch_prop_level(A, l, P->p_s, P->p_ang, P->opts.precision, g == 1, st));
+    float best[3] = {0, 0, 0};
+    int pick = kPropNode;
+    for (int g = kPropNode; g <= kPropSmall; ++g) {
+      HIP_TRY(launch_prop_level(A, l, P->p_s, P->p_ang, P->opts.precision, g, st));
       HIP_TRY(hipEventRecord(e0, st));
       for (int rep = 0; rep < 2; ++rep)
-        HIP_TRY(launch_prop_level(A, l, P->p_s, P->p_ang, P->opts.precision, g == 1, st));
+        HIP_TRY(launch_prop_level(A, l, P->p_s, P->p_ang, P->opts.precision, g, st));
       HIP_TRY(hipEventRecord(e1, st));
       HIP_TRY(hipEventSynchronize(e1));
       HIP_TRY(hipEventElapsedTime(&best[g], e0, e1));
+      if (best[g] < best[pick]) pick = g;
     }
-    Q.prop_grouped = best[1] < best[0] ? 1 : 0;
-    P->info.autotune_ms[l + 1][0] = best[0] / 2;
-    P->info.autotune_ms[l + 1][1] = best[1] / 2;
+    Q.prop_grouped = pick;
+    for (int g = 0; g < 3; ++g) P->info.autotune_ms[l + 1][g] = best[g] / 2;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -340,8 +341,9 @@ static void build_device(ifgf_plan_s* P) {
         HIP_TRY(hipMemcpy(hkeys.data(), keys, sizeof(unsigned long long) * count,
                           hipMemcpyDeviceToHost));
       const MergedStep& S = m.step[l];
-      D.prop_grouped = 0;
+      D.prop_grouped = kPropNode;
       D.nchunks = 0;
+      D.nschunks = 0;
       if (l >= 1 && count > 0) {
         const uint64_t ng = (uint64_t)D.ngrid;
         std::vector<int32_t> order(count);
@@ -354,9 +356,12 @@ static void build_device(ifgf_plan_s* P) {
           auto a = gk(x), b = gk(y);
           return a != b ? a < b : x < y;
         });
+        // Chunks of at most cbox (block kernel) and sbox (one-wave kernel)
+        // boxes sharing (instance, gamma).
         const int cbox = chunk_boxes(P->opts.precision, P->opts.n_rhs);
-        std::vector<int64_t> cstart;
-        std::vector<int32_t> clen;
+        const int sbox = small_chunk_boxes(P->opts.n_rhs);
+        std::vector<int64_t> cstart, sstart;
+        std::vector<int32_t> clen, slen;
         int64_t groups = 0;
         for (int64_t i = 0; i < (int64_t)count; ++i) {
           bool same = i > 0 && gk(order[i]) == gk(order[i - 1]);
@@ -366,15 +371,31 @@ static void build_device(ifgf_plan_s* P) {
             clen.push_back(0);
           }
           clen.back() += 1;
+          if (!same || slen.back() == sbox) {
+            sstart.push_back(i);
+            slen.push_back(0);
+          }
+          slen.back() += 1;
         }
+        // Without the autotuner: the block kernel where many boxes share a
+        // parent cone index, the one-wave kernel where a few do, the
+        // per-node kernel otherwise.
         double mean = (double)count / (double)std::max<int64_t>(groups, 1);
         int mode = P->opts.prop_kernel;
-        D.prop_grouped = PP <= kMfmaMaxP && (mode == 2 || (mode == 0 && mean >= 32.0));
-        if (PP <= kMfmaMaxP && (D.prop_grouped || P->opts.autotune)) {
+        if (PP <= kMfmaMaxP) {
+          if (mode == 2 || (mode == 0 && mean >= 32.0))
+            D.prop_grouped = kPropGrouped;
+          else if (mode == 3 || (mode == 0 && mean >= 4.0))
+            D.prop_grouped = kPropSmall;
+        }
+        if (PP <= kMfmaMaxP && (D.prop_grouped != kPropNode || P->opts.autotune)) {
           D.gslot = P->upload(order);
           D.chunk_start = P->upload(cstart);
           D.chunk_len = P->upload(clen);
           D.nchunks = (int64_t)cstart.size();
+          D.schunk_start = P->upload(sstart);
+          D.schunk_len = P->upload(slen);
+          D.nschunks = (int64_t)sstart.size();
         }
       }
       int64_t pairs_l = 0;
@@ -433,7 +454,7 @@ static void fill_info(ifgf_plan_s* P) {
     I.cousin_pairs[l] = pairs;
     I.grid[l] = (int64_t)(P->opts.leaf_grid[0] << l) * (P->opts.leaf_grid[1] << l) *
                 (P->opts.leaf_grid[2] << l);
-    I.prop_mode[l] = (l >= 1 && P->device_ready) ? (P->steps_h[l].prop_grouped ? 2 : 1) : 0;
+    I.prop_mode[l] = (l >= 1 && P->device_ready) ? P->steps_h[l].prop_grouped + 1 : 0;
   }
   I.near_pairs = m.near_pairs;
   I.device_bytes = P->bytes;

@@ -49,12 +49,18 @@ struct StepDev {
   // Propagation into this step, grouped: the relevant cones sorted by
   // (instance, gamma, box) and cut into chunks of boxes sharing one gamma,
   // whose node geometry is computed once per chunk.
-  int prop_grouped;           // 1: use the grouped propagation kernel
+  int prop_grouped;           // kernel: kPropNode, kPropGrouped or kPropSmall
   int64_t nchunks;
   const int* gslot;           // slots in (instance, gamma, box) order
   const int64_t* chunk_start; // first index into gslot of each chunk
   const int* chunk_len;       // boxes in each chunk (<= chunk_boxes())
+  int64_t nschunks;           // the same order cut into tasks of at most
+  const int64_t* schunk_start; // small_chunk_boxes() boxes (one wave each)
+  const int* schunk_len;
 };
+
+// Propagation kernels of a level.
+enum { kPropNode = 0, kPropGrouped = 1, kPropSmall = 2 };
 
 // Largest P = P_s P_ang^2 with a matrix-core propagation kernel.
 static constexpr int kMfmaMaxP = 125;
@@ -63,6 +69,8 @@ static constexpr int kMfmaMaxP = 125;
 // sub-chunks of 32 (FP32) or 16 (FP64) GEMM columns.
 static constexpr int kSubChunks = 8;
 int chunk_boxes(int precision, int nrhs);
+// Boxes per task of the one-wave matrix-core propagation (16 GEMM columns).
+int small_chunk_boxes(int nrhs);
 
 // Everything a kernel needs; passed by value (small), the per-step views
 // live in device memory.
@@ -128,10 +136,10 @@ hipError_t launch_build_lookup(const unsigned long long* keys, int64_t n,
 hipError_t sort_keys(unsigned long long* keys, unsigned long long* tmp,
                      int64_t n, int end_bit, void* scratch,
                      size_t* scratch_bytes, hipStream_t st);
-// One Propagation launch (step l -> l + 1) with the chosen kernel
-// (grouped = matrix-core form), for timing at plan time.
+// One Propagation launch (step l -> l + 1) with kernel `kind` (kPropNode,
+// kPropGrouped, kPropSmall), for timing at plan time.
 hipError_t launch_prop_level(const ApplyArgs& A, int l, int ps, int pa,
-                             int precision, bool grouped, hipStream_t st);
+                             int precision, int kind, hipStream_t st);
 hipError_t launch_apply(const ApplyArgs& A, int ps, int pa, int precision,
                         const void* dens_user, void* out_user, hipStream_t st,
                         Profiler* prof);
