@@ -187,12 +187,12 @@ def main():
     launches = st[dom][1] / args.steps
     avg_ms = st[dom][0] / st[dom][1]
     bound = "alu"
-    if dom in ("propagation", "propagation_mfma"):
-        mode = 2 if dom == "propagation_mfma" else 1
+    if dom in ("propagation", "propagation_mfma", "propagation_small"):
+        mode = {"propagation": 1, "propagation_mfma": 2, "propagation_small": 3}[dom]
         units = sum(pp for pp, md in zip(info["prop_pairs"], info["prop_mode"]) if md == mode)
         flop = units * n_rhs * flops_per_eval(P)
         unit_txt = "(parent-cone node, relevant child) evaluations"
-        bound = "mfma" if mode == 2 else "alu"
+        bound = "mfma" if mode >= 2 else "alu"
     elif dom == "interpolation":
         units = sum(info["cousin_pairs"])
         flop = units * n_rhs * flops_per_eval(P)

@@ -175,8 +175,9 @@ typedef enum {
   IFGF_STAGE_INTERPOLATION = 3, /* Interpolation(d), all levels */
   IFGF_STAGE_PROPAGATION = 4,   /* Propagation(d), per-node kernel levels */
   IFGF_STAGE_PERMUTE_OUT = 5,
-  IFGF_STAGE_PROPAGATION_MFMA = 6, /* Propagation(d), matrix-core levels */
-  IFGF_N_STAGES = 7
+  IFGF_STAGE_PROPAGATION_MFMA = 6, /* Propagation(d), matrix-core block levels */
+  IFGF_STAGE_PROPAGATION_SMALL = 7, /* Propagation(d), one-wave matrix-core levels */
+  IFGF_N_STAGES = 8
 } ifgf_stage;
 
 typedef struct ifgf_stage_times {

@@ -905,19 +905,23 @@ struct BigProp {
 
 // Decodes work item `item` of octant o (M-tiles of all child cones in
 // order, times N-tiles) into child cone k, row range and tile indices.
+// Decodes work item `item` of octant o (pairs of M-tiles of every child
+// cone in order, times N-tiles) into child cone k, first M-tile mt (even)
+// and N-tile nt.
 template <int P>
 __device__ __forceinline__ void big_item(const int* rbeg, int item, int ntn, int& k, int& mt,
                                          int& nt) {
   const int gm = item / ntn;
   nt = item - gm * ntn;
   k = 0;
-  mt = gm;
+  int mp = gm;
   for (;;) {
-    const int t = (rbeg[k + 1] - rbeg[k] + 15) / 16;
-    if (mt < t) break;
-    mt -= t;
+    const int t = (rbeg[k + 1] - rbeg[k] + 31) / 32;
+    if (mp < t) break;
+    mp -= t;
     ++k;
   }
+  mt = 2 * mp;
 }
 
 template <int PS, int PA, int MAXR>
@@ -966,6 +970,35 @@ __device__ __forceinline__ void big_load_b(const StepDev& S, const float2* __res
   }
 }
 
+// Accumulates ratio(p) * C of one 16 x 16 tile (rows of lane: pe, ratio
+// gc + i gs) into the LDS accumulators; the four reads go before the four
+// writes (distinct addresses).
+template <typename V4>
+__device__ __forceinline__ void big_epilogue(float* s_y, int yb, bool colok, const int* pe,
+                                             const float* gc, const float* gs, const V4& accr,
+                                             const V4& acci) {
+  if (!colok) return;
+  float y0[4], y1[4];
+#pragma unroll
+  for (int r4 = 0; r4 < 4; ++r4) {
+    y0[r4] = 0.f;
+    y1[r4] = 0.f;
+    if (pe[r4] >= 0) {
+      y0[r4] = s_y[2 * (yb + pe[r4])];
+      y1[r4] = s_y[2 * (yb + pe[r4]) + 1];
+    }
+  }
+#pragma unroll
+  for (int r4 = 0; r4 < 4; ++r4) {
+    if (pe[r4] >= 0) {
+      s_y[2 * (yb + pe[r4])] = y0[r4] + accr[r4] * gc[r4] - acci[r4] * gs[r4];
+      s_y[2 * (yb + pe[r4]) + 1] = y1[r4] + accr[r4] * gs[r4] + acci[r4] * gc[r4];
+    }
+  }
+}
+
+// One work item: M-tiles mt and (if it exists) mt + 1 of child cone k,
+// N-tile nt, sharing the B tile.
 template <int PS, int PA, int MAXR>
 __device__ __forceinline__ void big_compute(const float* s_A, const float* rat,
                                             const unsigned char* rows, const int* rbeg,
@@ -983,44 +1016,68 @@ __device__ __forceinline__ void big_compute(const float* s_A, const float* rat,
   const int n0 = col / nrhs;
   const int r = col - n0 * nrhs;
   const int yb = colok ? ((int)nl[n0] * MAXR + r) * P : 0;
-  // A operand: lane holds W[row 16 mt + lane % 16][q] with q the node of
-  // k-step kk for lane group kq.
-  const int arow = min(rb0 + mt * 16 + (lane & 15), P - 1);
-  const v4* ap = reinterpret_cast<const v4*>(s_A + arow * B::RS + kq * B::KS);
-  float av[B::KS];
+  const bool two = (mt + 1) * 16 < rlen;  // uniform across the wave
+  // A operands: lane holds W[row 16 t + lane % 16][q] with q the node of
+  // k-step kk for lane group kq, t = mt, mt + 1.
+  float av0[B::KS], av1[B::KS];
+  {
+    const int arow0 = min(rb0 + mt * 16 + (lane & 15), P - 1);
+    const int arow1 = min(rb0 + mt * 16 + 16 + (lane & 15), P - 1);
+    const v4* ap0 = reinterpret_cast<const v4*>(s_A + arow0 * B::RS + kq * B::KS);
+    const v4* ap1 = reinterpret_cast<const v4*>(s_A + arow1 * B::RS + kq * B::KS);
 #pragma unroll
-  for (int j = 0; j < B::KS / 4; ++j) {
-    const v4 v = ap[j];
-    av[4 * j] = v.x;
-    av[4 * j + 1] = v.y;
-    av[4 * j + 2] = v.z;
-    av[4 * j + 3] = v.w;
-  }
-  int pe[4];
-  float gc[4], gs[4];
+    for (int j = 0; j < B::KS / 4; ++j) {
+      const v4 v = ap0[j];
+      av0[4 * j] = v.x;
+      av0[4 * j + 1] = v.y;
+      av0[4 * j + 2] = v.z;
+      av0[4 * j + 3] = v.w;
+    }
+    if (two) {
 #pragma unroll
-  for (int r4 = 0; r4 < 4; ++r4) {
-    const int mm = mt * 16 + 4 * (lane >> 4) + r4;
-    const int pos = rb0 + (mm < rlen ? mm : 0);
-    pe[r4] = mm < rlen ? (int)rows[pos] : -1;
-    gc[r4] = rat[2 * pos];
-    gs[r4] = rat[2 * pos + 1];
-  }
-  v4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
-#pragma unroll
-  for (int kk = 0; kk < B::NK; ++kk) {
-    accr = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kk], br[kk], accr, 0, 0, 0);
-    acci = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kk], bi[kk], acci, 0, 0, 0);
-  }
-  if (colok) {
-#pragma unroll
-    for (int r4 = 0; r4 < 4; ++r4) {
-      if (pe[r4] >= 0) {
-        float* yy = s_y + 2 * (yb + pe[r4]);
-        yy[0] += accr[r4] * gc[r4] - acci[r4] * gs[r4];
-        yy[1] += accr[r4] * gs[r4] + acci[r4] * gc[r4];
+      for (int j = 0; j < B::KS / 4; ++j) {
+        const v4 v = ap1[j];
+        av1[4 * j] = v.x;
+        av1[4 * j + 1] = v.y;
+        av1[4 * j + 2] = v.z;
+        av1[4 * j + 3] = v.w;
       }
     }
+  }
+  int pe0[4], pe1[4];
+  float gc0[4], gs0[4], gc1[4], gs1[4];
+#pragma unroll
+  for (int r4 = 0; r4 < 4; ++r4) {
+    const int mm0 = mt * 16 + 4 * (lane >> 4) + r4;
+    const int mm1 = mm0 + 16;
+    const int pos0 = rb0 + (mm0 < rlen ? mm0 : 0);
+    const int pos1 = rb0 + (mm1 < rlen ? mm1 : 0);
+    pe0[r4] = mm0 < rlen ? (int)rows[pos0] : -1;
+    pe1[r4] = mm1 < rlen ? (int)rows[pos1] : -1;
+    gc0[r4] = rat[2 * pos0];
+    gs0[r4] = rat[2 * pos0 + 1];
+    gc1[r4] = rat[2 * pos1];
+    gs1[r4] = rat[2 * pos1 + 1];
+  }
+  if (two) {
+    v4 ar0 = {0, 0, 0, 0}, ai0 = {0, 0, 0, 0}, ar1 = {0, 0, 0, 0}, ai1 = {0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < B::NK; ++kk) {
+      ar0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av0[kk], br[kk], ar0, 0, 0, 0);
+      ai0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av0[kk], bi[kk], ai0, 0, 0, 0);
+      ar1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av1[kk], br[kk], ar1, 0, 0, 0);
+      ai1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av1[kk], bi[kk], ai1, 0, 0, 0);
+    }
+    big_epilogue(s_y, yb, colok, pe0, gc0, gs0, ar0, ai0);
+    big_epilogue(s_y, yb, colok, pe1, gc1, gs1, ar1, ai1);
+  } else {
+    v4 ar0 = {0, 0, 0, 0}, ai0 = {0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < B::NK; ++kk) {
+      ar0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av0[kk], br[kk], ar0, 0, 0, 0);
+      ai0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av0[kk], bi[kk], ai0, 0, 0, 0);
+    }
+    big_epilogue(s_y, yb, colok, pe0, gc0, gs0, ar0, ai0);
   }
 }
 
@@ -1225,7 +1282,7 @@ prop_big_kernel(ApplyArgs A, int l, const float2* __restrict__ Vc, float2* __res
       __syncthreads();
       const int* rbeg = s_rbeg + o * (P + 1);
       int nmt = 0;
-      for (int k = 0; k < s_na[o]; ++k) nmt += (rbeg[k + 1] - rbeg[k] + 15) / 16;
+      for (int k = 0; k < s_na[o]; ++k) nmt += (rbeg[k + 1] - rbeg[k] + 31) / 32;
       const int nitem = nmt * ntn;
       if (wave < nitem) {
         float br0[B::NK], bi0[B::NK], br1[B::NK], bi1[B::NK];
@@ -1296,7 +1353,7 @@ struct SmallProp {
 };
 
 template <int PS, int PA, typename T, int MAXR>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64, 2)
 prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc,
                   typename C2<T>::type* __restrict__ Vp) {
   typedef SmallProp<PS, PA, T, MAXR> SP;
@@ -1474,7 +1531,8 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
     const int nn = colok ? n0 : 0;
     const int r = colok ? col - n0 * nrhs : 0;
     const int yb = colok ? ((int)s_nl[o][nn] * MAXR + r) * P : 0;
-    for (int k = 0; k < na; ++k) {
+    // B tile of child cone k (lane: column col, nodes of lane group kq).
+    auto load_b = [&](int k, T* br, T* bi) {
       int cs;
       if (k < NAMAX) {
         cs = s_cs[nn * NAMAX + k];
@@ -1483,7 +1541,6 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
         if (cs < 0) atomicOr(A.err, 1);
       }
       const CT* vp = Vc + ((int64_t)(cs >= 0 ? cs : 0) * nrhs + r) * P;
-      T br[NK], bi[NK];
       if constexpr (SP::PAIRS) {
         typedef T v4u __attribute__((ext_vector_type(4), aligned(8)));
 #pragma unroll
@@ -1516,6 +1573,9 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
           bi[kk] = x.y;
         }
       }
+    };
+    // Every M-tile of child cone k.
+    auto tiles = [&](int k, const T* br, const T* bi) {
       const int rb0 = s_rbeg[k], rlen = s_rbeg[k + 1] - rb0;
       for (int mt = 0; mt * 16 < rlen; ++mt) {
         const int arow = min(rb0 + mt * 16 + (lane & 15), P - 1);
@@ -1553,6 +1613,11 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
           }
         }
       }
+    };
+    for (int k = 0; k < na; ++k) {
+      T br[NK], bi[NK];
+      load_b(k, br, bi);
+      tiles(k, br, bi);
     }
     __syncthreads();
   }
@@ -1886,7 +1951,7 @@ static hipError_t apply_impl(const ApplyArgs& A, const void* dens_user,
             IFGF_TIMED(6, (launch_grouped<PS, PA, T, MAXR>(A, l, Vcur, Vnext, Qh.nchunks, st)));
             done = true;
           } else if (Qh.prop_grouped == kPropSmall) {
-            IFGF_TIMED(6, (prop_small_kernel<PS, PA, T, MAXR>
+            IFGF_TIMED(7, (prop_small_kernel<PS, PA, T, MAXR>
                            <<<(unsigned)Qh.nschunks, 64, 0, st>>>(A, l, Vcur, Vnext)));
             done = true;
           }

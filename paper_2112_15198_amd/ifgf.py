@@ -27,7 +27,7 @@ EXPORTED = ["ifgf_default_opts", "ifgf_plan", "ifgf_plan_ex", "ifgf_plan_batched
             "ifgf_apply_graph"]
 
 STAGES = ["permute_in", "near_field", "leaf", "interpolation", "propagation",
-          "permute_out", "propagation_mfma"]
+          "permute_out", "propagation_mfma", "propagation_small"]
 
 
 class Opts(ctypes.Structure):
