@@ -188,8 +188,9 @@ def main():
     avg_ms = st[dom][0] / st[dom][1]
     bound = "alu"
     if dom in ("propagation", "propagation_mfma", "propagation_small"):
-        mode = {"propagation": 1, "propagation_mfma": 2, "propagation_small": 3}[dom]
-        units = sum(pp for pp, md in zip(info["prop_pairs"], info["prop_mode"]) if md == mode)
+        modes = {"propagation": (1,), "propagation_mfma": (2,), "propagation_small": (3, 4)}[dom]
+        mode = modes[0]
+        units = sum(pp for pp, md in zip(info["prop_pairs"], info["prop_mode"]) if md in modes)
         flop = units * n_rhs * flops_per_eval(P)
         unit_txt = "(parent-cone node, relevant child) evaluations"
         bound = "mfma" if mode >= 2 else "alu"

@@ -68,15 +68,16 @@ typedef struct ifgf_opts {
   int device;       /* HIP device ordinal; -1 uses the current device */
   void* stream;     /* hipStream_t used by ifgf_apply; NULL = null stream */
   int prop_kernel;  /* propagation kernel per level: 0 chooses by the mean
-                       number of boxes sharing a parent cone index (>= 32:
-                       matrix-core blocks; >= 4: one-wave matrix-core tasks;
-                       else per-node), 1 forces the per-node form, 2 the
-                       matrix-core block form, 3 the one-wave matrix-core
-                       form */
+                       number of boxes sharing a parent cone index (>= 160:
+                       matrix-core blocks; >= 32: four-wave matrix-core
+                       tasks; >= 4: one-wave matrix-core tasks; else
+                       per-node), 1 forces the per-node form, 2 the
+                       matrix-core block form, 3 the one-wave task form,
+                       4 the four-wave task form */
   int lookup;       /* cone look-up: 0 dense tables where a level's table
                        (boxes x cone grid) has <= 2^28 entries, hash tables
                        elsewhere; 1 hash tables everywhere */
-  int autotune;     /* 1: at plan time, time the three propagation kernels
+  int autotune;     /* 1: at plan time, time the four propagation kernels
                        on every level where the matrix-core forms apply and
                        keep the fastest (overrides prop_kernel there) */
   double cone_margin; /* a point within cone_margin cone widths of a cone
@@ -104,11 +105,11 @@ typedef struct ifgf_info {
                                          step l (l >= 1) */
   int prop_mode[IFGF_MAX_LEVELS];      /* kernel of Propagation into step l:
                                          1 per-node, 2 matrix-core blocks,
-                                         3 one-wave matrix-core tasks */
-  float autotune_ms[IFGF_MAX_LEVELS][3]; /* autotuner timings of Propagation
-                                         into step l: per-node, matrix-core
-                                         blocks, one-wave matrix-core (0 when
-                                         not tuned) */
+                                         3 one-wave matrix-core tasks,
+                                         4 four-wave matrix-core tasks */
+  float autotune_ms[IFGF_MAX_LEVELS][4]; /* autotuner timings of Propagation
+                                         into step l, kernels 1..4 in order
+                                         (0 when not tuned) */
   int64_t leaf_pairs;     /* (leaf-cone node, source) evaluations of
                              LevelDEvaluations */
   int64_t near_pairs;     /* (target, source) near-field pairs, self included */
@@ -176,7 +177,7 @@ typedef enum {
   IFGF_STAGE_PROPAGATION = 4,   /* Propagation(d), per-node kernel levels */
   IFGF_STAGE_PERMUTE_OUT = 5,
   IFGF_STAGE_PROPAGATION_MFMA = 6, /* Propagation(d), matrix-core block levels */
-  IFGF_STAGE_PROPAGATION_SMALL = 7, /* Propagation(d), one-wave matrix-core levels */
+  IFGF_STAGE_PROPAGATION_SMALL = 7, /* Propagation(d), wave-task matrix-core levels */
   IFGF_N_STAGES = 8
 } ifgf_stage;
 

@@ -118,7 +118,7 @@ static ifgf_status validate(int p_s, int p_ang, const ifgf_opts& o) {
       return fail(IFGF_EINVAL, "leaf_grid entries must be in [1, 4096]");
   if (o.levels != 0 && o.levels < 3) return fail(IFGF_EINVAL, "levels must be 0 or >= 3");
   if (o.stages < 0 || o.stages > 3) return fail(IFGF_EINVAL, "stages must be in [0, 3]");
-  if (o.prop_kernel < 0 || o.prop_kernel > 3) return fail(IFGF_EINVAL, "prop_kernel must be 0, 1, 2 or 3");
+  if (o.prop_kernel < 0 || o.prop_kernel > 4) return fail(IFGF_EINVAL, "prop_kernel must be 0..4");
   if (o.lookup < 0 || o.lookup > 1) return fail(IFGF_EINVAL, "lookup must be 0 or 1");
   if (!(o.cone_margin >= 0.0 && o.cone_margin < 0.25))
     return fail(IFGF_EINVAL, "cone_margin must be in [0, 0.25)");
@@ -151,7 +151,7 @@ static void cheb_nodes(int n, double* t, double* w) {
   }
 }
 
-// Time the three propagation kernels on every level where the matrix-core
+// Time the four propagation kernels on every level where the matrix-core
 // forms apply (zeroed cone values: the kernels' work does not depend on the
 // values) and keep the fastest.
 static void autotune(ifgf_plan_s* P) {
@@ -170,9 +170,9 @@ static void autotune(ifgf_plan_s* P) {
   for (int l = 0; l + 1 < A.n_steps; ++l) {
     StepDev& Q = P->steps_h[l + 1];
     if (Q.ncones == 0 || Q.nchunks == 0) continue;
-    float best[3] = {0, 0, 0};
+    float best[4] = {0, 0, 0, 0};
     int pick = kPropNode;
-    for (int g = kPropNode; g <= kPropSmall; ++g) {
+    for (int g = kPropNode; g <= kPropMedium; ++g) {
       HIP_TRY(launch_prop_level(A, l, P->p_s, P->p_ang, P->opts.precision, g, st));
       HIP_TRY(hipEventRecord(e0, st));
       for (int rep = 0; rep < 2; ++rep)
@@ -183,7 +183,7 @@ static void autotune(ifgf_plan_s* P) {
       if (best[g] < best[pick]) pick = g;
     }
     Q.prop_grouped = pick;
-    for (int g = 0; g < 3; ++g) P->info.autotune_ms[l + 1][g] = best[g] / 2;
+    for (int g = 0; g < 4; ++g) P->info.autotune_ms[l + 1][g] = best[g] / 2;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -344,6 +344,7 @@ static void build_device(ifgf_plan_s* P) {
       D.prop_grouped = kPropNode;
       D.nchunks = 0;
       D.nschunks = 0;
+      D.nmchunks = 0;
       if (l >= 1 && count > 0) {
         const uint64_t ng = (uint64_t)D.ngrid;
         std::vector<int32_t> order(count);
@@ -359,9 +360,10 @@ static void build_device(ifgf_plan_s* P) {
         // Chunks of at most cbox (block kernel) and sbox (one-wave kernel)
         // boxes sharing (instance, gamma).
         const int cbox = chunk_boxes(P->opts.precision, P->opts.n_rhs);
-        const int sbox = small_chunk_boxes(P->opts.n_rhs);
-        std::vector<int64_t> cstart, sstart;
-        std::vector<int32_t> clen, slen;
+        const int sbox = small_chunk_boxes(P->opts.n_rhs, 1);
+        const int mbox = small_chunk_boxes(P->opts.n_rhs, kMediumWaves);
+        std::vector<int64_t> cstart, sstart, mstart;
+        std::vector<int32_t> clen, slen, mlen;
         int64_t groups = 0;
         for (int64_t i = 0; i < (int64_t)count; ++i) {
           bool same = i > 0 && gk(order[i]) == gk(order[i - 1]);
@@ -376,15 +378,23 @@ static void build_device(ifgf_plan_s* P) {
             slen.push_back(0);
           }
           slen.back() += 1;
+          if (!same || mlen.back() == mbox) {
+            mstart.push_back(i);
+            mlen.push_back(0);
+          }
+          mlen.back() += 1;
         }
         // Without the autotuner: the block kernel where many boxes share a
-        // parent cone index, the one-wave kernel where a few do, the
-        // per-node kernel otherwise.
+        // parent cone index (>= 160 on average), the four-wave task kernel
+        // where some do (>= 32), the one-wave task kernel where a few do
+        // (>= 4), the per-node kernel otherwise.
         double mean = (double)count / (double)std::max<int64_t>(groups, 1);
         int mode = P->opts.prop_kernel;
         if (PP <= kMfmaMaxP) {
-          if (mode == 2 || (mode == 0 && mean >= 32.0))
+          if (mode == 2 || (mode == 0 && mean >= 160.0))
             D.prop_grouped = kPropGrouped;
+          else if (mode == 4 || (mode == 0 && mean >= 32.0))
+            D.prop_grouped = kPropMedium;
           else if (mode == 3 || (mode == 0 && mean >= 4.0))
             D.prop_grouped = kPropSmall;
         }
@@ -396,6 +406,9 @@ static void build_device(ifgf_plan_s* P) {
           D.schunk_start = P->upload(sstart);
           D.schunk_len = P->upload(slen);
           D.nschunks = (int64_t)sstart.size();
+          D.mchunk_start = P->upload(mstart);
+          D.mchunk_len = P->upload(mlen);
+          D.nmchunks = (int64_t)mstart.size();
         }
       }
       int64_t pairs_l = 0;

@@ -54,13 +54,18 @@ struct StepDev {
   const int* gslot;           // slots in (instance, gamma, box) order
   const int64_t* chunk_start; // first index into gslot of each chunk
   const int* chunk_len;       // boxes in each chunk (<= chunk_boxes())
-  int64_t nschunks;           // the same order cut into tasks of at most
-  const int64_t* schunk_start; // small_chunk_boxes() boxes (one wave each)
+  int64_t nschunks;           // the same order cut into chunks of at most
+  const int64_t* schunk_start; // small_chunk_boxes(nrhs, 1) boxes (one wave)
   const int* schunk_len;
+  int64_t nmchunks;           // ... and of small_chunk_boxes(nrhs, kMediumWaves)
+  const int64_t* mchunk_start;
+  const int* mchunk_len;
 };
 
-// Propagation kernels of a level.
-enum { kPropNode = 0, kPropGrouped = 1, kPropSmall = 2 };
+// Propagation kernels of a level: per node, matrix-core blocks, one-wave
+// matrix-core tasks, kMediumWaves-wave matrix-core tasks.
+enum { kPropNode = 0, kPropGrouped = 1, kPropSmall = 2, kPropMedium = 3 };
+static constexpr int kMediumWaves = 4;
 
 // Largest P = P_s P_ang^2 with a matrix-core propagation kernel.
 static constexpr int kMfmaMaxP = 125;
@@ -69,8 +74,9 @@ static constexpr int kMfmaMaxP = 125;
 // sub-chunks of 32 (FP32) or 16 (FP64) GEMM columns.
 static constexpr int kSubChunks = 8;
 int chunk_boxes(int precision, int nrhs);
-// Boxes per task of the one-wave matrix-core propagation (16 GEMM columns).
-int small_chunk_boxes(int nrhs);
+// Boxes per chunk of the wave-task matrix-core propagation: 16 GEMM columns
+// per wave.
+int small_chunk_boxes(int nrhs, int waves);
 
 // Everything a kernel needs; passed by value (small), the per-step views
 // live in device memory.

@@ -928,7 +928,8 @@ template <int PS, int PA, int MAXR>
 __device__ __forceinline__ void big_load_b(const StepDev& S, const float2* __restrict__ Vc,
                                            int* err, const int* cs_tab, const int* ch_tab,
                                            const int* dist, const int* rbeg, int item, int ntn,
-                                           int ncols, int nrhs, int lane, float* br, float* bi) {
+                                           int ncols, int nrhs, int lane, bool live, float* br,
+                                           float* bi) {
   typedef BigProp<PS, PA, MAXR> B;
   constexpr int P = B::P;
   int k, mt, nt;
@@ -944,7 +945,7 @@ __device__ __forceinline__ void big_load_b(const StepDev& S, const float2* __res
     cs = cone_lookup(S, (unsigned long long)ch_tab[n] * S.ngrid + dist[k]);
     if (cs < 0) atomicOr(err, 1);
   }
-  const float2* vp = Vc + ((int64_t)(cs >= 0 ? cs : 0) * nrhs + r) * P;
+  const float2* vp = live ? Vc + ((int64_t)(cs >= 0 ? cs : 0) * nrhs + r) * P : Vc;
   typedef float v4u __attribute__((ext_vector_type(4), aligned(8)));
 #pragma unroll
   for (int m = 0; m < B::NPAIR; ++m) {
@@ -1286,22 +1287,24 @@ prop_big_kernel(ApplyArgs A, int l, const float2* __restrict__ Vc, float2* __res
       const int nitem = nmt * ntn;
       if (wave < nitem) {
         float br0[B::NK], bi0[B::NK], br1[B::NK], bi1[B::NK];
-#define IFGF_BIG_LOAD(IT, BR, BI)                                                           \
+#define IFGF_BIG_LOAD(IT, LIVE, BR, BI)                                                     \
   big_load_b<PS, PA, MAXR>(S, Vc, A.err, s_cs[buf], s_child[o], s_dist + o * P, rbeg, IT, ntn,  \
-                           ncols, nrhs, lane, BR, BI)
+                           ncols, nrhs, lane, LIVE, BR, BI)
 #define IFGF_BIG_COMP(IT, BR, BI)                                                         \
   big_compute<PS, PA, MAXR>(s_A, s_rat + 2 * o * P, s_rows + o * P, rbeg, s_nl[o], s_y, IT, \
                             ntn, ncols, nrhs, lane, BR, BI)
+        // Past the wave's last item the prefetch reads one line that every
+        // lane shares, and is not used.
         int item = wave;
-        IFGF_BIG_LOAD(item, br0, bi0);
+        IFGF_BIG_LOAD(item, true, br0, bi0);
         for (;;) {
           const int i1 = item + NWV < nitem ? item + NWV : item;
-          IFGF_BIG_LOAD(i1, br1, bi1);
+          IFGF_BIG_LOAD(i1, i1 != item, br1, bi1);
           IFGF_BIG_COMP(item, br0, bi0);
           if (i1 == item) break;
           item = i1;
           const int i2 = item + NWV < nitem ? item + NWV : item;
-          IFGF_BIG_LOAD(i2, br0, bi0);
+          IFGF_BIG_LOAD(i2, i2 != item, br0, bi0);
           IFGF_BIG_COMP(item, br1, bi1);
           if (i2 == item) break;
           item = i2;
@@ -1326,22 +1329,25 @@ prop_big_kernel(ApplyArgs A, int l, const float2* __restrict__ Vc, float2* __res
   }
 }
 
-// Matrix-core propagation for levels where few boxes share a parent cone
-// index: one wave per task of up to WB parent boxes sharing (instance,
-// gamma').  Octant by octant the wave computes the node geometry (child
-// cone, local coordinates, ratio) of the 75 nodes, groups the nodes by child
-// cone, forms their Lagrange factors in LDS, and multiplies
+// Matrix-core propagation for levels where few to some hundred boxes share
+// a parent cone index.  A block of NWV waves takes a chunk of up to NWV * WB
+// parent boxes sharing (instance, gamma'); wave w owns the boxes
+// w WB .. w WB + WB - 1 and accumulates their cones in its own LDS slice.
+// Octant by octant the block computes the node geometry (child cone, local
+// coordinates, ratio) of the nodes, groups them by child cone and forms
+// their Lagrange factors in LDS, once for all its waves; every wave then
+// multiplies
 //     C[p][(box, rhs)] = sum_q W[p][q] X[q][(box, rhs)]
-// on 16x16x4 MFMA tiles (one N-tile: the task's boxes with a child in the
+// on 16x16x4 MFMA tiles (one N-tile: its boxes with a child in the
 // octant), W[p][q] = (L_a L_b)(u_s, u_theta) * L_c(u_phi) formed per tile
-// from the LDS factors.  ratio(p) * C accumulates in the wave's LDS slice.
-// FP32: K order in pairs of adjacent nodes (16-byte loads of two complex
-// values); FP64: q = 4 kk + kq (one complex value per 16-byte load).
+// from the LDS factors, and adds ratio(p) * C to its slice.  FP32: K order
+// in pairs of adjacent nodes (16-byte loads of two complex values); FP64:
+// q = 4 kk + kq (one complex value per 16-byte load).
 template <int PS, int PA, typename T, int MAXR>
 struct SmallProp {
   static constexpr int P = PS * PA * PA;
   static constexpr int NK = (P + 3) / 4;
-  static constexpr int WB = 16 / MAXR;        // boxes per task
+  static constexpr int WB = 16 / MAXR;        // boxes per wave
   static constexpr int NAMAX = 8;             // child cones per octant with a cached slot
   static constexpr int LW = PS * PA + PA + 1; // (L_a L_b) products, L_c, zero
   static constexpr bool PAIRS = sizeof(T) == 4;
@@ -1353,7 +1359,105 @@ struct SmallProp {
 };
 
 template <int PS, int PA, typename T, int MAXR>
-__global__ void __launch_bounds__(64, 2)
+__device__ __forceinline__ void small_load_b(const typename C2<T>::type* __restrict__ vp, int kq,
+                                             T* br, T* bi) {
+  typedef SmallProp<PS, PA, T, MAXR> SP;
+  typedef typename C2<T>::type CT;
+  constexpr int P = SP::P, NK = SP::NK;
+  if constexpr (SP::PAIRS) {
+    typedef T v4u __attribute__((ext_vector_type(4), aligned(8)));
+#pragma unroll
+    for (int m = 0; m < SP::NPAIR; ++m) {
+      if (8 * m + 7 < P) {
+        const v4u x = *reinterpret_cast<const v4u*>(vp + 8 * m + 2 * kq);
+        br[2 * m] = x.x;
+        bi[2 * m] = x.y;
+        br[2 * m + 1] = x.z;
+        bi[2 * m + 1] = x.w;
+      } else {
+        const CT x0 = vp[min(8 * m + 2 * kq, P - 1)];
+        const CT x1 = vp[min(8 * m + 2 * kq + 1, P - 1)];
+        br[2 * m] = x0.x;
+        bi[2 * m] = x0.y;
+        br[2 * m + 1] = x1.x;
+        bi[2 * m + 1] = x1.y;
+      }
+    }
+    if constexpr (NK & 1) {
+      const CT x = vp[min(8 * SP::NPAIR + kq, P - 1)];
+      br[NK - 1] = x.x;
+      bi[NK - 1] = x.y;
+    }
+  } else {
+#pragma unroll
+    for (int kk = 0; kk < NK; ++kk) {
+      const CT x = vp[min(4 * kk + kq, P - 1)];
+      br[kk] = x.x;
+      bi[kk] = x.y;
+    }
+  }
+}
+
+// Every M-tile of one child cone (rows rb0 .. rb0 + rlen - 1 of the
+// octant's grouping) times the B tile, added with the ratio into the
+// wave's accumulators y.
+template <int PS, int PA, typename T, int MAXR>
+__device__ __forceinline__ void small_tiles(const T* s_L, const T* s_rat,
+                                            const unsigned char* s_rows, T* y,
+                                            const unsigned* qreg, int rb0, int rlen, int yb,
+                                            bool colok, int lane, const T* br, const T* bi) {
+  typedef SmallProp<PS, PA, T, MAXR> SP;
+  typedef typename Mfma<T>::v4 V4;
+  constexpr int P = SP::P, NK = SP::NK, LW = SP::LW;
+  for (int mt = 0; mt * 16 < rlen; ++mt) {
+    const int arow = min(rb0 + mt * 16 + (lane & 15), P - 1);
+    const T* L = s_L + arow * LW;
+    T av[NK];
+#pragma unroll
+    for (int kk = 0; kk < NK; ++kk) {
+      const unsigned qi = qreg[kk];
+      av[kk] = L[qi & 0xff] * L[qi >> 8];
+    }
+    int pe[4];
+    T gc[4], gs[4];
+#pragma unroll
+    for (int r4 = 0; r4 < 4; ++r4) {
+      const int mm = mt * 16 + Mfma<T>::row(lane, r4);
+      const int pos = rb0 + (mm < rlen ? mm : 0);
+      pe[r4] = mm < rlen ? (int)s_rows[pos] : -1;
+      gc[r4] = s_rat[2 * pos];
+      gs[r4] = s_rat[2 * pos + 1];
+    }
+    V4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < NK; ++kk) {
+      accr = Mfma<T>::mma(av[kk], br[kk], accr);
+      acci = Mfma<T>::mma(av[kk], bi[kk], acci);
+    }
+    if (colok) {
+      T y0[4], y1[4];
+#pragma unroll
+      for (int r4 = 0; r4 < 4; ++r4) {
+        y0[r4] = (T)0;
+        y1[r4] = (T)0;
+        if (pe[r4] >= 0) {
+          y0[r4] = y[2 * (yb + pe[r4])];
+          y1[r4] = y[2 * (yb + pe[r4]) + 1];
+        }
+      }
+#pragma unroll
+      for (int r4 = 0; r4 < 4; ++r4) {
+        if (pe[r4] >= 0) {
+          y[2 * (yb + pe[r4])] = y0[r4] + accr[r4] * gc[r4] - acci[r4] * gs[r4];
+          y[2 * (yb + pe[r4]) + 1] = y1[r4] + accr[r4] * gs[r4] + acci[r4] * gc[r4];
+        }
+      }
+    }
+  }
+}
+
+template <int PS, int PA, typename T, int MAXR, int NWV>
+__global__ void __launch_bounds__(64 * NWV, 2)
 prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc,
                   typename C2<T>::type* __restrict__ Vp) {
   typedef SmallProp<PS, PA, T, MAXR> SP;
@@ -1361,25 +1465,32 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
   typedef typename Mfma<T>::v4 V4;
   constexpr int P = SP::P, NK = SP::NK, WB = SP::WB, NAMAX = SP::NAMAX, LW = SP::LW;
   static_assert(P <= 128, "two nodes per lane");
-  __shared__ T s_y[WB * MAXR * P * 2];
+  // Shared per octant.
   __shared__ T s_L[P * LW];                 // factors of the node at grouped position pos
   __shared__ T s_rat[P * 2];                // ratio at pos
   __shared__ T s_u[P * 3];                  // local coordinates of node p
   __shared__ T s_ratp[P * 2];               // ratio of node p
+  __shared__ int s_alpha[P];                // child cone of node p
   __shared__ unsigned char s_rows[P];       // node p at pos
   __shared__ int s_rbeg[P + 1];
   __shared__ int s_dist[P];                 // distinct child cones
-  __shared__ int s_slot[WB];
-  __shared__ int s_ch[8][WB];               // children per octant, compacted
-  __shared__ unsigned char s_nl[8][WB];     // their box index in the task
-  __shared__ int s_cs[WB * NAMAX];          // child cone slots of the current octant
+  __shared__ int s_na;
+  __shared__ unsigned s_om[NWV];            // octants with children, per wave
+  // Per wave.
+  __shared__ T s_y[NWV][WB * MAXR * P * 2];
+  __shared__ int s_slot[NWV][WB];
+  __shared__ int s_ch[NWV][8][WB];          // children per octant, compacted
+  __shared__ unsigned char s_nl[NWV][8][WB]; // their box index in the wave's task
+  __shared__ int s_cs[NWV][WB * NAMAX];     // child cone slots of the current octant
 
   const StepDev& S = A.step[l];
   const StepDev& Q = A.step[l + 1];
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nrhs = A.nrhs;
-  const int64_t g0 = Q.schunk_start[blockIdx.x];
-  const int nb = Q.schunk_len[blockIdx.x];
+  const int64_t* cstart = NWV == 1 ? Q.schunk_start : Q.mchunk_start;
+  const int* clen = NWV == 1 ? Q.schunk_len : Q.mchunk_len;
+  const int64_t g0 = cstart[blockIdx.x];
+  const int nbw = max(0, min(WB, clen[blockIdx.x] - wave * WB));  // boxes of this wave
   const unsigned long long key0 = Q.cone_key[Q.gslot[g0]];
   const int64_t j0 = (int64_t)(key0 / (unsigned long long)Q.ngrid);
   const int64_t g = (int64_t)(key0 - (unsigned long long)j0 * Q.ngrid);
@@ -1392,29 +1503,33 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
   const double Hc = S.inst_H[inst];
   const double kappa = A.inst_kappa[inst];
   const unsigned long long lt = (1ull << lane) - 1ull;
+  T* const y = s_y[wave];
 
-  // Boxes of the task and their children, compacted per octant.
+  // The wave's boxes and their children, compacted per octant.
   int box = 0;
-  if (lane < nb) {
-    const int slot = Q.gslot[g0 + lane];
-    s_slot[lane] = slot;
+  if (lane < nbw) {
+    const int slot = Q.gslot[g0 + wave * WB + lane];
+    s_slot[wave][lane] = slot;
     box = (int)(Q.cone_key[slot] / (unsigned long long)Q.ngrid);
   }
   int ch[8];
 #pragma unroll
-  for (int o = 0; o < 8; ++o) ch[o] = lane < nb ? Q.child[8 * (int64_t)box + o] : -1;
-  for (int i = lane; i < WB * MAXR * P * 2; i += 64) s_y[i] = (T)0;
+  for (int o = 0; o < 8; ++o) ch[o] = lane < nbw ? Q.child[8 * (int64_t)box + o] : -1;
+  for (int i = lane; i < WB * MAXR * P * 2; i += 64) y[i] = (T)0;
   int nos[8];
+  unsigned om = 0;
 #pragma unroll
   for (int o = 0; o < 8; ++o) {
     const unsigned long long m = __ballot(ch[o] >= 0);
     if (ch[o] >= 0) {
       const int pos = __popcll(m & lt);
-      s_ch[o][pos] = ch[o];
-      s_nl[o][pos] = (unsigned char)lane;
+      s_ch[wave][o][pos] = ch[o];
+      s_nl[wave][o][pos] = (unsigned char)lane;
     }
     nos[o] = __popcll(m);
+    if (m) om |= 1u << o;
   }
+  if (lane == 0) s_om[wave] = om;
   // Per lane: for each k-step, the offsets of (L_a L_b) and L_c of its node
   // q in a row of s_L (the zero slot for q >= P).
   unsigned qreg[NK];
@@ -1425,58 +1540,58 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
                      : (unsigned)(LW - 1) | ((unsigned)(LW - 1) << 8);
   }
   __syncthreads();
+  unsigned omall = 0;
+#pragma unroll
+  for (int w = 0; w < NWV; ++w) omall |= s_om[w];
 
+  const int col = lane & 15, kq = lane >> 4;
 #pragma unroll 1
   for (int o = 0; o < 8; ++o) {
-    const int no = nos[o];
-    if (no == 0) continue;
-    // Node geometry of octant o; lane holds nodes lane and lane + 64.
-    int al[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int p = lane + 64 * h;
-      al[h] = -1;
-      if (p < P) {
-        const int a = p / (PA * PA), bb = (p / PA) % PA, cc = p % PA;
-        double yp[3];
-        node_offset<PS, PA>(Q, hp, is, it, ip, a, bb, cc, yp);
-        double y0, y1, y2, rj;
-        {
-          IFGF_NO_CONTRACT
-          y0 = yp[0] - (((o >> 2) & 1) ? 0.5 * Hc : -0.5 * Hc);
-          y1 = yp[1] - (((o >> 1) & 1) ? 0.5 * Hc : -0.5 * Hc);
-          y2 = yp[2] - ((o & 1) ? 0.5 * Hc : -0.5 * Hc);
-          rj = sqrt(yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]);
-        }
-        ConeCoord cr = cone_coord(S, hc, y0, y1, y2);
-        double u0, u1, u2;
-        const int cs = cone_index(cr.q[0], S.ns, u0);
-        const int ct = cone_index(cr.q[1], S.nt, u1);
-        const int cp = cone_index(cr.q[2], S.np, u2);
-        al[h] = (cs * S.nt + ct) * S.np + cp;
-        s_u[3 * p] = (T)u0;
-        s_u[3 * p + 1] = (T)u1;
-        s_u[3 * p + 2] = (T)u2;
-        T gcv, gsv;
-        expi<T>(kappa * (cr.r - rj), gcv, gsv);
-        const T amp = (T)(rj / cr.r);
-        s_ratp[2 * p] = gcv * amp;
-        s_ratp[2 * p + 1] = gsv * amp;
+    if (!((omall >> o) & 1u)) continue;  // uniform across the block
+    // Node geometry of octant o.
+    for (int p = tid; p < P; p += 64 * NWV) {
+      const int a = p / (PA * PA), bb = (p / PA) % PA, cc = p % PA;
+      double yp[3];
+      node_offset<PS, PA>(Q, hp, is, it, ip, a, bb, cc, yp);
+      double y0, y1, y2, rj;
+      {
+        IFGF_NO_CONTRACT
+        y0 = yp[0] - (((o >> 2) & 1) ? 0.5 * Hc : -0.5 * Hc);
+        y1 = yp[1] - (((o >> 1) & 1) ? 0.5 * Hc : -0.5 * Hc);
+        y2 = yp[2] - ((o & 1) ? 0.5 * Hc : -0.5 * Hc);
+        rj = sqrt(yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]);
       }
+      ConeCoord cr = cone_coord(S, hc, y0, y1, y2);
+      double u0, u1, u2;
+      const int cs = cone_index(cr.q[0], S.ns, u0);
+      const int ct = cone_index(cr.q[1], S.nt, u1);
+      const int cp = cone_index(cr.q[2], S.np, u2);
+      s_alpha[p] = (cs * S.nt + ct) * S.np + cp;
+      s_u[3 * p] = (T)u0;
+      s_u[3 * p + 1] = (T)u1;
+      s_u[3 * p + 2] = (T)u2;
+      T gcv, gsv;
+      expi<T>(kappa * (cr.r - rj), gcv, gsv);
+      const T amp = (T)(rj / cr.r);
+      s_ratp[2 * p] = gcv * amp;
+      s_ratp[2 * p + 1] = gsv * amp;
     }
-    // Distinct child cones and the nodes grouped by child cone (ballots).
-    int na = 0;
-    {
+    __syncthreads();
+    // Distinct child cones and the nodes grouped by child cone (wave 0,
+    // ballots; lane holds nodes lane and lane + 64).
+    if (wave == 0) {
       const bool has0 = lane < P, has1 = lane + 64 < P;
+      const int a0 = has0 ? s_alpha[lane] : -1;
+      const int a1 = has1 ? s_alpha[lane + 64] : -1;
       bool f0 = has0, f1 = has1;
-      int k0 = 0, k1 = 0;
+      int k0 = 0, k1 = 0, na = 0;
       for (;;) {
         const unsigned long long m0 = __ballot(f0), m1 = __ballot(f1);
         if (m0 == 0ull && m1 == 0ull) break;
-        const int lead = m0 ? __shfl(al[0], __ffsll((long long)m0) - 1)
-                            : __shfl(al[1], __ffsll((long long)m1) - 1);
-        if (f0 && al[0] == lead) { k0 = na; f0 = false; }
-        if (f1 && al[1] == lead) { k1 = na; f1 = false; }
+        const int lead = m0 ? __shfl(a0, __ffsll((long long)m0) - 1)
+                            : __shfl(a1, __ffsll((long long)m1) - 1);
+        if (f0 && a0 == lead) { k0 = na; f0 = false; }
+        if (f1 && a1 == lead) { k1 = na; f1 = false; }
         if (lane == 0) s_dist[na] = lead;
         ++na;
       }
@@ -1488,148 +1603,85 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
         if (lane == 0) s_rbeg[k] = base;
         base += __popcll(m0) + __popcll(m1);
       }
-      if (lane == 0) s_rbeg[na] = base;
+      if (lane == 0) {
+        s_rbeg[na] = base;
+        s_na = na;
+      }
     }
     __syncthreads();
-    // Factors in grouped order; child cone slots of the task's children.
+    const int na = s_na;
+    const int no = nos[o];
+    // Factors in grouped order (block); child cone slots of the wave's
+    // children.
+    for (int pos = tid; pos < P; pos += 64 * NWV) {
+      const int p = s_rows[pos];
+      T La[PS], Lb[PA], Lc[PA];
+      lagrange<PS, T>(s_u[3 * p], A.cheb.ts, A.cheb.ws, La);
+      lagrange<PA, T>(s_u[3 * p + 1], A.cheb.ta, A.cheb.wa, Lb);
+      lagrange<PA, T>(s_u[3 * p + 2], A.cheb.ta, A.cheb.wa, Lc);
+      T* L = s_L + pos * LW;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int pos = lane + 64 * h;
-      if (pos < P) {
-        const int p = s_rows[pos];
-        T La[PS], Lb[PA], Lc[PA];
-        lagrange<PS, T>(s_u[3 * p], A.cheb.ts, A.cheb.ws, La);
-        lagrange<PA, T>(s_u[3 * p + 1], A.cheb.ta, A.cheb.wa, Lb);
-        lagrange<PA, T>(s_u[3 * p + 2], A.cheb.ta, A.cheb.wa, Lc);
-        T* L = s_L + pos * LW;
+      for (int a = 0; a < PS; ++a)
 #pragma unroll
-        for (int a = 0; a < PS; ++a)
+        for (int b = 0; b < PA; ++b) L[a * PA + b] = La[a] * Lb[b];
 #pragma unroll
-          for (int b = 0; b < PA; ++b) L[a * PA + b] = La[a] * Lb[b];
-#pragma unroll
-        for (int c = 0; c < PA; ++c) L[PS * PA + c] = Lc[c];
-        L[LW - 1] = (T)0;
-        s_rat[2 * pos] = s_ratp[2 * p];
-        s_rat[2 * pos + 1] = s_ratp[2 * p + 1];
-      }
+      for (int c = 0; c < PA; ++c) L[PS * PA + c] = Lc[c];
+      L[LW - 1] = (T)0;
+      s_rat[2 * pos] = s_ratp[2 * p];
+      s_rat[2 * pos + 1] = s_ratp[2 * p + 1];
     }
     {
       const int nac = min(na, NAMAX);
       for (int e = lane; e < no * nac; e += 64) {
         const int k = e / no, n = e - k * no;
-        const int cs = cone_lookup(S, (unsigned long long)s_ch[o][n] * S.ngrid + s_dist[k]);
+        const int cs = cone_lookup(S, (unsigned long long)s_ch[wave][o][n] * S.ngrid + s_dist[k]);
         if (cs < 0) atomicOr(A.err, 1);
-        s_cs[n * NAMAX + k] = cs;
+        s_cs[wave][n * NAMAX + k] = cs;
       }
     }
     __syncthreads();
-    // Groups (child cone k): B tile once, then every M-tile of k.
-    const int ncols = no * nrhs;
-    const int col = lane & 15, kq = lane >> 4;
-    const bool colok = col < ncols;
-    const int n0 = col / nrhs;
-    const int nn = colok ? n0 : 0;
-    const int r = colok ? col - n0 * nrhs : 0;
-    const int yb = colok ? ((int)s_nl[o][nn] * MAXR + r) * P : 0;
-    // B tile of child cone k (lane: column col, nodes of lane group kq).
-    auto load_b = [&](int k, T* br, T* bi) {
-      int cs;
-      if (k < NAMAX) {
-        cs = s_cs[nn * NAMAX + k];
-      } else {
-        cs = cone_lookup(S, (unsigned long long)s_ch[o][nn] * S.ngrid + s_dist[k]);
-        if (cs < 0) atomicOr(A.err, 1);
+    if (no > 0) {
+      const int ncols = no * nrhs;
+      const bool colok = col < ncols;
+      const int n0 = col / nrhs;
+      const int nn = colok ? n0 : 0;
+      const int r = colok ? col - n0 * nrhs : 0;
+      const int yb = colok ? ((int)s_nl[wave][o][nn] * MAXR + r) * P : 0;
+      // B tile of child cone KK (lane: column col, nodes of lane group kq).
+#define IFGF_SMALL_LOAD(KK, LIVE, BR, BI)                                                  \
+  do {                                                                                     \
+    int cs_;                                                                               \
+    if ((KK) < NAMAX) {                                                                    \
+      cs_ = s_cs[wave][nn * NAMAX + (KK)];                                                 \
+    } else {                                                                               \
+      cs_ = cone_lookup(S, (unsigned long long)s_ch[wave][o][nn] * S.ngrid + s_dist[KK]);  \
+      if (cs_ < 0) atomicOr(A.err, 1);                                                     \
+    }                                                                                      \
+    small_load_b<PS, PA, T, MAXR>(                                                         \
+        LIVE ? Vc + ((int64_t)(cs_ >= 0 ? cs_ : 0) * nrhs + r) * P : Vc, kq, BR, BI);      \
+  } while (0)
+#define IFGF_SMALL_TILES(KK, BR, BI)                                                      \
+  small_tiles<PS, PA, T, MAXR>(s_L, s_rat, s_rows, y, qreg, s_rbeg[KK],                    \
+                               s_rbeg[(KK) + 1] - s_rbeg[KK], yb, colok, lane, BR, BI)
+      for (int k = 0; k < na; ++k) {
+        T br[NK], bi[NK];
+        IFGF_SMALL_LOAD(k, true, br, bi);
+        IFGF_SMALL_TILES(k, br, bi);
       }
-      const CT* vp = Vc + ((int64_t)(cs >= 0 ? cs : 0) * nrhs + r) * P;
-      if constexpr (SP::PAIRS) {
-        typedef T v4u __attribute__((ext_vector_type(4), aligned(8)));
-#pragma unroll
-        for (int m = 0; m < SP::NPAIR; ++m) {
-          if (8 * m + 7 < P) {
-            const v4u x = *reinterpret_cast<const v4u*>(vp + 8 * m + 2 * kq);
-            br[2 * m] = x.x;
-            bi[2 * m] = x.y;
-            br[2 * m + 1] = x.z;
-            bi[2 * m + 1] = x.w;
-          } else {
-            const CT x0 = vp[min(8 * m + 2 * kq, P - 1)];
-            const CT x1 = vp[min(8 * m + 2 * kq + 1, P - 1)];
-            br[2 * m] = x0.x;
-            bi[2 * m] = x0.y;
-            br[2 * m + 1] = x1.x;
-            bi[2 * m + 1] = x1.y;
-          }
-        }
-        if constexpr (NK & 1) {
-          const CT x = vp[min(8 * SP::NPAIR + kq, P - 1)];
-          br[NK - 1] = x.x;
-          bi[NK - 1] = x.y;
-        }
-      } else {
-#pragma unroll
-        for (int kk = 0; kk < NK; ++kk) {
-          const CT x = vp[min(4 * kk + kq, P - 1)];
-          br[kk] = x.x;
-          bi[kk] = x.y;
-        }
-      }
-    };
-    // Every M-tile of child cone k.
-    auto tiles = [&](int k, const T* br, const T* bi) {
-      const int rb0 = s_rbeg[k], rlen = s_rbeg[k + 1] - rb0;
-      for (int mt = 0; mt * 16 < rlen; ++mt) {
-        const int arow = min(rb0 + mt * 16 + (lane & 15), P - 1);
-        const T* L = s_L + arow * LW;
-        T av[NK];
-#pragma unroll
-        for (int kk = 0; kk < NK; ++kk) {
-          const unsigned qi = qreg[kk];
-          av[kk] = L[qi & 0xff] * L[qi >> 8];
-        }
-        int pe[4];
-        T gc[4], gs[4];
-#pragma unroll
-        for (int r4 = 0; r4 < 4; ++r4) {
-          const int mm = mt * 16 + Mfma<T>::row(lane, r4);
-          const int pos = rb0 + (mm < rlen ? mm : 0);
-          pe[r4] = mm < rlen ? (int)s_rows[pos] : -1;
-          gc[r4] = s_rat[2 * pos];
-          gs[r4] = s_rat[2 * pos + 1];
-        }
-        V4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
-#pragma unroll
-        for (int kk = 0; kk < NK; ++kk) {
-          accr = Mfma<T>::mma(av[kk], br[kk], accr);
-          acci = Mfma<T>::mma(av[kk], bi[kk], acci);
-        }
-        if (colok) {
-#pragma unroll
-          for (int r4 = 0; r4 < 4; ++r4) {
-            if (pe[r4] >= 0) {
-              T* yy = s_y + 2 * (yb + pe[r4]);
-              yy[0] += accr[r4] * gc[r4] - acci[r4] * gs[r4];
-              yy[1] += accr[r4] * gs[r4] + acci[r4] * gc[r4];
-            }
-          }
-        }
-      }
-    };
-    for (int k = 0; k < na; ++k) {
-      T br[NK], bi[NK];
-      load_b(k, br, bi);
-      tiles(k, br, bi);
+#undef IFGF_SMALL_LOAD
+#undef IFGF_SMALL_TILES
     }
     __syncthreads();
   }
-  // Write the parent cones of the task.
-  for (int i = lane; i < nb * nrhs * P; i += 64) {
+  // Write the parent cones of the wave's boxes.
+  for (int i = lane; i < nbw * nrhs * P; i += 64) {
     const int n = i / (nrhs * P);
     const int rem = i - n * (nrhs * P);
     const int r = rem / P, p = rem - (rem / P) * P;
     CT v;
-    v.x = s_y[2 * ((n * MAXR + r) * P + p)];
-    v.y = s_y[2 * ((n * MAXR + r) * P + p) + 1];
-    Vp[((int64_t)s_slot[n] * nrhs + r) * P + p] = v;
+    v.x = y[2 * ((n * MAXR + r) * P + p)];
+    v.y = y[2 * ((n * MAXR + r) * P + p) + 1];
+    Vp[((int64_t)s_slot[wave][n] * nrhs + r) * P + p] = v;
   }
 }
 
@@ -1897,7 +1949,7 @@ hipError_t sort_keys(unsigned long long* keys, unsigned long long* tmp,
     }                                                              \
   } while (0)
 
-int small_chunk_boxes(int nrhs) { return 16 / (nrhs <= 1 ? 1 : kMaxRhs); }
+int small_chunk_boxes(int nrhs, int waves) { return waves * (16 / (nrhs <= 1 ? 1 : kMaxRhs)); }
 
 int chunk_boxes(int precision, int nrhs) {
   const int maxr = nrhs <= 1 ? 1 : kMaxRhs;
@@ -1951,8 +2003,13 @@ static hipError_t apply_impl(const ApplyArgs& A, const void* dens_user,
             IFGF_TIMED(6, (launch_grouped<PS, PA, T, MAXR>(A, l, Vcur, Vnext, Qh.nchunks, st)));
             done = true;
           } else if (Qh.prop_grouped == kPropSmall) {
-            IFGF_TIMED(7, (prop_small_kernel<PS, PA, T, MAXR>
+            IFGF_TIMED(7, (prop_small_kernel<PS, PA, T, MAXR, 1>
                            <<<(unsigned)Qh.nschunks, 64, 0, st>>>(A, l, Vcur, Vnext)));
+            done = true;
+          } else if (Qh.prop_grouped == kPropMedium) {
+            IFGF_TIMED(7, (prop_small_kernel<PS, PA, T, MAXR, kMediumWaves>
+                           <<<(unsigned)Qh.nmchunks, 64 * kMediumWaves, 0, st>>>(A, l, Vcur,
+                                                                                 Vnext)));
             done = true;
           }
         }
@@ -1985,7 +2042,12 @@ static hipError_t prop_level_impl(const ApplyArgs& A, int l, int kind,
       return hipGetLastError();
     }
     if (kind == kPropSmall && Qh.nschunks > 0) {
-      prop_small_kernel<PS, PA, T, MAXR><<<(unsigned)Qh.nschunks, 64, 0, st>>>(A, l, Vc, Vp);
+      prop_small_kernel<PS, PA, T, MAXR, 1><<<(unsigned)Qh.nschunks, 64, 0, st>>>(A, l, Vc, Vp);
+      return hipGetLastError();
+    }
+    if (kind == kPropMedium && Qh.nmchunks > 0) {
+      prop_small_kernel<PS, PA, T, MAXR, kMediumWaves>
+          <<<(unsigned)Qh.nmchunks, 64 * kMediumWaves, 0, st>>>(A, l, Vc, Vp);
       return hipGetLastError();
     }
   }

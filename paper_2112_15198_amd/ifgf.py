@@ -50,7 +50,7 @@ class Info(ctypes.Structure):
                 ("grid", ctypes.c_int64 * IFGF_MAX_LEVELS),
                 ("prop_pairs", ctypes.c_int64 * IFGF_MAX_LEVELS),
                 ("prop_mode", ctypes.c_int * IFGF_MAX_LEVELS),
-                ("autotune_ms", (ctypes.c_float * 3) * IFGF_MAX_LEVELS),
+                ("autotune_ms", (ctypes.c_float * 4) * IFGF_MAX_LEVELS),
                 ("leaf_pairs", ctypes.c_int64),
                 ("near_pairs", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("plan_seconds", ctypes.c_double)]
@@ -124,8 +124,8 @@ def _opts(precision, n_rhs, leaf_grid, levels, stages, host_only, device,
     o.device = -1 if device is None else int(device)
     if cone_margin is not None:
         o.cone_margin = float(cone_margin)
-    o.prop_kernel = {"auto": 0, "node": 1, "grouped": 2, "small": 3,
-                     0: 0, 1: 1, 2: 2, 3: 3}[prop_kernel]
+    o.prop_kernel = {"auto": 0, "node": 1, "grouped": 2, "small": 3, "medium": 4,
+                     0: 0, 1: 1, 2: 2, 3: 3, 4: 4}[prop_kernel]
     o.lookup = {"auto": 0, "hash": 1, 0: 0, 1: 1}[lookup]
     o.autotune = 1 if autotune else 0
     return o

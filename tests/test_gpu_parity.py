@@ -120,7 +120,7 @@ def test_other_orders_match_oracle(ps, pa):
     assert relerr(g[0], o) <= 1e-10
 
 
-@pytest.mark.parametrize("prop", ["auto", "grouped", "small", "node"])
+@pytest.mark.parametrize("prop", ["auto", "grouped", "small", "medium", "node"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_multi_rhs_equals_single_rhs(precision, prop):
     n = 6000
@@ -224,12 +224,13 @@ def test_relevant_cones_match_oracle_exactly(geom):
 
 @pytest.mark.parametrize("prop,lookup", [("node", "auto"), ("grouped", "auto"),
                                          ("grouped", "hash"), ("node", "hash"),
-                                         ("small", "auto"), ("small", "hash")])
+                                         ("small", "auto"), ("small", "hash"),
+                                         ("medium", "auto")])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 2e-5)])
 def test_kernel_variants_match_oracle(prop, lookup, precision, tol):
-    """Per-node, matrix-core block and one-wave matrix-core propagation, dense
-    and hashed cone look-up: all agree with the oracle IFGF (FP64: 1e-10;
-    FP32-mixed: 2e-5, its rounding)."""
+    """Per-node, matrix-core block and wave-task (one and four waves)
+    propagation, dense and hashed cone look-up: all agree with the oracle
+    IFGF (FP64: 1e-10; FP32-mixed: 2e-5, its rounding)."""
     n = 7000
     p = W.fibonacci_sphere(n)
     k = W.kappa_sphere_10ppw(n)
@@ -240,7 +241,7 @@ def test_kernel_variants_match_oracle(prop, lookup, precision, tol):
     assert relerr(g[0], o) <= tol
 
 
-@pytest.mark.parametrize("prop", ["grouped", "small"])
+@pytest.mark.parametrize("prop", ["grouped", "small", "medium"])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
 def test_graph_replays_match_eager(precision, tol, prop):
     """The HIP-graph apply, replayed several times with eager work and
@@ -285,6 +286,6 @@ def test_autotune_picks_a_kernel_per_level_and_stays_exact():
     for l in tuned:
         t = info["autotune_ms"][l]
         assert all(x > 0 for x in t), t
-        assert info["prop_mode"][l] == 1 + min(range(3), key=lambda g: t[g])
+        assert info["prop_mode"][l] == 1 + min(range(4), key=lambda g: t[g])
     o = oracle.ifgf(p, a[0], k, leaf_grid=(2, 4, 8))
     assert relerr(g[0], o) <= 1e-10
