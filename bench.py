@@ -119,8 +119,8 @@ def main():
                     help="skip the CPU oracle (baseline and error check)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(multi-GPU sharding is not part of this build)", flush=True)
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported",
+              flush=True)
         sys.exit(2)
 
     import torch

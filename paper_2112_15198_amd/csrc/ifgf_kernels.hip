@@ -27,6 +27,8 @@
 // the phase argument kappa*r reduction in FP64).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cstdint>
 #include <cstring>
 #include <rocprim/device/device_radix_sort.hpp>
@@ -40,8 +42,10 @@ namespace ifgf {
 static constexpr double kPiD = 3.14159265358979323846;
 static constexpr double kInv2Pi = 0.15915494309189533577;
 
+// Flat thread index of a launch whose grid is split over x and y (so that
+// each dimension stays within the dispatch's 32-bit work-item count).
 __device__ __forceinline__ int64_t gtid() {
-  return (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  return ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
 }
 
 __device__ __forceinline__ unsigned long long hmix(unsigned long long x) {
@@ -1866,8 +1870,12 @@ __global__ void build_lookup_kernel(const unsigned long long* __restrict__ keys,
 // Host-side launchers.
 // ---------------------------------------------------------------------------
 
-static inline unsigned nblk(int64_t n, int bs) {
-  return (unsigned)((n + bs - 1) / bs);
+// Grid covering n threads in blocks of bs: at most 2^22 blocks in x (2^30
+// work-items), the rest in y; threads past n exit in the kernels.
+static inline dim3 nblk(int64_t n, int bs) {
+  const int64_t b = std::max<int64_t>(1, (n + bs - 1) / bs);
+  const int64_t bx = std::min<int64_t>(b, int64_t(1) << 22);
+  return dim3((unsigned)bx, (unsigned)((b + bx - 1) / bx), 1);
 }
 
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n,
