@@ -157,9 +157,12 @@ def main():
             pl = ifgf.plan(w.points, w.kappa, p_s=p_s, p_ang=p_ang, precision=prec,
                            n_rhs=n_rhs, leaf_grid=grid, autotune=True)
         plan_s = time.perf_counter() - t0
+        print(f"# {prec}: plan {plan_s:.2f} s (N={n}, D={pl.info()['D']})",
+              file=sys.stderr, flush=True)
         dt = torch.complex64 if prec == "fp32" else torch.complex128
         a = torch.from_numpy(dens).to(dt).cuda()
         ms_eager, _ = time_applies(pl, a, args.steps, args.warmup, graph=False)
+        print(f"# {prec}: eager {ms_eager:.3f} ms/apply", file=sys.stderr, flush=True)
         stages = stage_times(pl, a, args.steps)
         ms, out = time_applies(pl, a, args.steps, args.warmup, graph=True)
         info = pl.info()

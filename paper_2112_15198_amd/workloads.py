@@ -88,7 +88,7 @@ def _instance(name, pts, kappa, n_rhs, seed, n_samples):
                     {"N": n, "n_rhs": n_rhs, "seed": seed})
 
 
-# The five workloads.  Keys name what each workload is.
+# The workloads.  Keys name what each workload is.
 WORKLOADS = {
     # N=5,024 unit-sphere lattice, kappa = 4 pi (4 wavelengths across).
     "sphere_5k": dict(kind="sphere", n=5024, kappa=4.0 * math.pi, n_rhs=1,
@@ -105,6 +105,15 @@ WORKLOADS = {
     # N=5,144,576 unit-sphere lattice, kappa = 128 pi.
     "sphere_5m": dict(kind="sphere", n=5144576, kappa=128.0 * math.pi,
                       n_rhs=1, seed=1005, n_samples=4096),
+    # The paper's single-node test geometries (Section "Numerical results"),
+    # sized by their diameter d in wavelengths: the oblate spheroid
+    # x^2 + y^2 + (z/0.1)^2 = 1 at d = 2 = 128 lambda (kappa = 128 pi) and
+    # the prolate spheroid x^2 + y^2 + (z/10)^2 = 1 at d = 20 = 256 lambda
+    # (kappa = 25.6 pi), with the paper's point counts.
+    "oblate01_128l": dict(kind="spheroid", axes=(1.0, 1.0, 0.1), n=1572864,
+                          kappa=128.0 * math.pi, n_rhs=1, seed=1006, n_samples=4096),
+    "prolate10_256l": dict(kind="spheroid", axes=(1.0, 1.0, 10.0), n=6291456,
+                           kappa=25.6 * math.pi, n_rhs=1, seed=1007, n_samples=4096),
 }
 
 
@@ -120,6 +129,9 @@ def make(name: str, n_rhs: int | None = None, n_samples: int | None = None):
                          w["n_rhs"], w["seed"], w["n_samples"])
     if w["kind"] == "oblate":
         return _instance(name, spheroid(w["n"]), w["kappa"], w["n_rhs"],
+                         w["seed"], w["n_samples"])
+    if w["kind"] == "spheroid":
+        return _instance(name, spheroid(w["n"], w["axes"]), w["kappa"], w["n_rhs"],
                          w["seed"], w["n_samples"])
     if w["kind"] == "batch":
         return make_batch(w["n_inst"], w["n_min"], w["n_max"], w["n_rhs"],

@@ -89,11 +89,22 @@ def test_far_field_alone_fp64():
     assert relerr(g[0], o) <= 1e-10
 
 
-@pytest.mark.parametrize("geom", ["oblate", "clusters", "deep"])
+def _paper_spheroid(geom, n):
+    """The paper's (1,1,0.1) and (1,1,10) spheroids at 12 wavelengths across
+    their diameters (2 and 20)."""
+    if geom == "oblate01":
+        return W.spheroid(n, (1.0, 1.0, 0.1)), 12.0 * math.pi
+    return W.spheroid(n, (1.0, 1.0, 10.0)), 1.2 * math.pi
+
+
+@pytest.mark.parametrize("geom", ["oblate", "clusters", "deep", "oblate01", "prolate10"])
 def test_fp64_matches_oracle_geometries(geom):
     if geom == "oblate":
         n = 12000
         p, k, lv = W.spheroid(n), W.kappa_oblate_10ppw(n), 0
+    elif geom in ("oblate01", "prolate10"):
+        p, k = _paper_spheroid(geom, 8000)
+        lv = 0
     elif geom == "clusters":
         rng = np.random.default_rng(3)
         p = np.vstack([rng.normal(size=(1500, 3)) * 0.05 - [1.0, 0, 0],
@@ -106,6 +117,21 @@ def test_fp64_matches_oracle_geometries(geom):
     g, _ = run_gpu(p, a, k, levels=lv)
     o = oracle.ifgf(p, a[0], k, leaf_grid=(2, 4, 8), levels=lv)
     assert relerr(g[0], o) <= 1e-10
+
+
+@pytest.mark.parametrize("geom", ["oblate01", "prolate10"])
+def test_fp32_paper_spheroids(geom):
+    """FP32-mixed on the paper's spheroids (autotuned kernels): the oracle
+    IFGF to 2e-5 (FP32 rounding) and the direct sum to 1e-3 (the method's
+    error on these anisotropic point sets)."""
+    p, k = _paper_spheroid(geom, 8000)
+    a = W.densities(len(p), 1, 36)
+    say("fp32 paper spheroid", geom)
+    g, _ = run_gpu(p, a, k, precision="fp32", autotune=True)
+    o = oracle.ifgf(p, a[0], k, leaf_grid=(2, 4, 8))
+    assert relerr(g[0], o) <= 2e-5
+    d = oracle.direct_sum(p, a[0], k)
+    assert relerr(g[0], d) <= 1e-3
 
 
 @pytest.mark.parametrize("ps,pa", [(2, 3), (5, 7)])

@@ -35,6 +35,10 @@ GEOMS = {
     "sphere": lambda: (W.fibonacci_sphere(3000), W.kappa_sphere_10ppw(3000)),
     "oblate": lambda: (W.spheroid(3000), W.kappa_oblate_10ppw(3000)),
     "clusters": lambda: (_two_clusters(), 12.0),
+    # The paper's test spheroids (1,1,0.1) and (1,1,10) at 8 wavelengths
+    # across their diameters d = 2 and d = 20.
+    "oblate01": lambda: (W.spheroid(3000, (1.0, 1.0, 0.1)), 8.0 * math.pi),
+    "prolate10": lambda: (W.spheroid(3000, (1.0, 1.0, 10.0)), 0.8 * math.pi),
 }
 
 
