@@ -106,10 +106,13 @@ WORKLOADS = {
     "sphere_5m": dict(kind="sphere", n=5144576, kappa=128.0 * math.pi,
                       n_rhs=1, seed=1005, n_samples=4096),
     # The paper's single-node test geometries (Section "Numerical results"),
-    # sized by their diameter d in wavelengths: the oblate spheroid
-    # x^2 + y^2 + (z/0.1)^2 = 1 at d = 2 = 128 lambda (kappa = 128 pi) and
+    # sized by their diameter d in wavelengths, with the paper's point
+    # counts: the unit sphere and the oblate spheroid
+    # x^2 + y^2 + (z/0.1)^2 = 1 at d = 2 = 128 lambda (kappa = 128 pi), and
     # the prolate spheroid x^2 + y^2 + (z/10)^2 = 1 at d = 20 = 256 lambda
-    # (kappa = 25.6 pi), with the paper's point counts.
+    # (kappa = 25.6 pi).
+    "sphere_128l": dict(kind="sphere", n=1572864, kappa=128.0 * math.pi, n_rhs=1,
+                        seed=1008, n_samples=4096),
     "oblate01_128l": dict(kind="spheroid", axes=(1.0, 1.0, 0.1), n=1572864,
                           kappa=128.0 * math.pi, n_rhs=1, seed=1006, n_samples=4096),
     "prolate10_256l": dict(kind="spheroid", axes=(1.0, 1.0, 10.0), n=6291456,
