@@ -1338,122 +1338,163 @@ prop_big_kernel(ApplyArgs A, int l, const float2* __restrict__ Vc, float2* __res
 // parent boxes sharing (instance, gamma'); wave w owns the boxes
 // w WB .. w WB + WB - 1 and accumulates their cones in its own LDS slice.
 // Octant by octant the block computes the node geometry (child cone, local
-// coordinates, ratio) of the nodes, groups them by child cone and forms
-// their Lagrange factors in LDS, once for all its waves; every wave then
-// multiplies
+// coordinates, ratio) of the nodes and groups them by child cone, once for
+// all its waves; every wave then multiplies
 //     C[p][(box, rhs)] = sum_q W[p][q] X[q][(box, rhs)]
 // on 16x16x4 MFMA tiles (one N-tile: its boxes with a child in the
-// octant), W[p][q] = (L_a L_b)(u_s, u_theta) * L_c(u_phi) formed per tile
-// from the LDS factors, and adds ratio(p) * C to its slice.  FP32: K order
-// in pairs of adjacent nodes (16-byte loads of two complex values); FP64:
-// q = 4 kk + kq (one complex value per 16-byte load).
+// octant), W[p][q] = L_a(u_s) L_b(u_theta) L_c(u_phi) formed per tile, and
+// adds ratio(p) * C to its slice.  The factors L_a, L_b, L_c of a row come
+// from LDS (several waves: formed once per octant) or are evaluated in
+// registers per tile (one wave: the LDS they would take keeps a third wave
+// per SIMD resident).
+//
+// K order.  A k-step is (g, c) with c the phi index of the node; its four
+// lane groups kq take four (a, b) pairs: for g < PS the pair (g, kq)
+// (kq < min(PA, 4)), for g = PS + e the pair (kq, 4 + e) (kq < PS), other
+// slots have weight 0.  A lane's weights are then L_c(c) times L_a(g) L_b(kq)
+// or L_a(kq) L_b(4 + e), so it selects one L_a and one L_b value per tile,
+// and its B values for each g are PA adjacent nodes of the child cone.
 template <int PS, int PA, typename T, int MAXR>
 struct SmallProp {
   static constexpr int P = PS * PA * PA;
-  static constexpr int NK = (P + 3) / 4;
+  static constexpr int PB = PA < 4 ? PA : 4;  // b = kq in the first PS groups
+  static constexpr int NE = PA > 4 ? PA - 4 : 0;  // groups with b = 4 + e, a = kq
+  static constexpr int NG = PS + NE;
+  static constexpr int NK = NG * PA;          // k-steps (g, c)
   static constexpr int WB = 16 / MAXR;        // boxes per wave
   static constexpr int NAMAX = 8;             // child cones per octant with a cached slot
-  static constexpr int LW = PS * PA + PA + 1; // (L_a L_b) products, L_c, zero
-  static constexpr bool PAIRS = sizeof(T) == 4;
-  static constexpr int NPAIR = PAIRS ? NK / 2 : 0;
-  static __device__ __forceinline__ int qnode(int kk, int kq) {
-    if (!PAIRS) return 4 * kk + kq;
-    return kk < 2 * NPAIR ? 8 * (kk >> 1) + 2 * kq + (kk & 1) : 8 * NPAIR + kq;
+  // s_L row: the slot products L_a L_b at kq NG + g, then L_c; 16 bytes.
+  static constexpr int LW = (4 * NG + PA + 3) / 4 * 4;
+  static_assert(PS <= 4 && PA <= 8, "slot mapping");
+  // (a, b) of slot (g, kq), false for a zero slot.
+  static __device__ __forceinline__ bool slot_ab(int g, int kq, int& a, int& b) {
+    a = g < PS ? g : kq;
+    b = g < PS ? kq : 4 + (g - PS);
+    return g < PS ? kq < PB : kq < PS;
+  }
+  // First node index (a PA + b) PA of slot (g, kq), or -1 for a zero slot.
+  static __device__ __forceinline__ int slot_row(int g, int kq) {
+    int a, b;
+    return slot_ab(g, kq, a, b) ? (a * PA + b) * PA : -1;
   }
 };
 
+// One Lagrange basis function L_j(u) = w_j prod_{m != j} (u - t_m) for a
+// lane-dependent j (a product over all m, no indexed registers).
+template <int N, typename T>
+__device__ __forceinline__ T lagrange_at(T u, const double* t, int j, T wj) {
+  T prod = wj;
+#pragma unroll
+  for (int m = 0; m < N; ++m) prod *= m == j ? (T)1 : u - (T)t[m];
+  return prod;
+}
+
+// B values of one lane (column of vp, lane group kq), in k-step order.
 template <int PS, int PA, typename T, int MAXR>
 __device__ __forceinline__ void small_load_b(const typename C2<T>::type* __restrict__ vp, int kq,
                                              T* br, T* bi) {
   typedef SmallProp<PS, PA, T, MAXR> SP;
   typedef typename C2<T>::type CT;
-  constexpr int P = SP::P, NK = SP::NK;
-  if constexpr (SP::PAIRS) {
-    typedef T v4u __attribute__((ext_vector_type(4), aligned(8)));
 #pragma unroll
-    for (int m = 0; m < SP::NPAIR; ++m) {
-      if (8 * m + 7 < P) {
-        const v4u x = *reinterpret_cast<const v4u*>(vp + 8 * m + 2 * kq);
-        br[2 * m] = x.x;
-        bi[2 * m] = x.y;
-        br[2 * m + 1] = x.z;
-        bi[2 * m + 1] = x.w;
-      } else {
-        const CT x0 = vp[min(8 * m + 2 * kq, P - 1)];
-        const CT x1 = vp[min(8 * m + 2 * kq + 1, P - 1)];
-        br[2 * m] = x0.x;
-        bi[2 * m] = x0.y;
-        br[2 * m + 1] = x1.x;
-        bi[2 * m + 1] = x1.y;
+  for (int g = 0; g < SP::NG; ++g) {
+    const int q0 = SP::slot_row(g, kq);
+    const CT* src = vp + (q0 >= 0 ? q0 : 0);  // zero slot: weight 0
+    if constexpr (sizeof(T) == 4) {
+      typedef T v4u __attribute__((ext_vector_type(4), aligned(8)));
+#pragma unroll
+      for (int c = 0; c + 1 < PA; c += 2) {
+        const v4u x = *reinterpret_cast<const v4u*>(src + c);
+        br[g * PA + c] = x.x;
+        bi[g * PA + c] = x.y;
+        br[g * PA + c + 1] = x.z;
+        bi[g * PA + c + 1] = x.w;
       }
-    }
-    if constexpr (NK & 1) {
-      const CT x = vp[min(8 * SP::NPAIR + kq, P - 1)];
-      br[NK - 1] = x.x;
-      bi[NK - 1] = x.y;
-    }
-  } else {
+      if constexpr (PA & 1) {
+        const CT x = src[PA - 1];
+        br[g * PA + PA - 1] = x.x;
+        bi[g * PA + PA - 1] = x.y;
+      }
+    } else {
 #pragma unroll
-    for (int kk = 0; kk < NK; ++kk) {
-      const CT x = vp[min(4 * kk + kq, P - 1)];
-      br[kk] = x.x;
-      bi[kk] = x.y;
+      for (int c = 0; c < PA; ++c) {
+        const CT x = src[c];
+        br[g * PA + c] = x.x;
+        bi[g * PA + c] = x.y;
+      }
     }
   }
 }
 
 // Every M-tile of one child cone (rows rb0 .. rb0 + rlen - 1 of the
 // octant's grouping) times the B tile, added with the ratio into the
-// wave's accumulators y.
-template <int PS, int PA, typename T, int MAXR>
-__device__ __forceinline__ void small_tiles(const T* s_L, const T* s_rat,
-                                            const unsigned char* s_rows, T* y,
-                                            const unsigned* qreg, int rb0, int rlen, int yb,
+// wave's accumulators y.  LREG: factors evaluated from s_u (node order)
+// instead of read from s_L (grouped order); wak, wbk are the weights of
+// L_a(kq), L_b(kq).
+template <int PS, int PA, typename T, int MAXR, bool LREG>
+__device__ __forceinline__ void small_tiles(const T* s_L, const T* s_u, const ChebConst& cheb,
+                                            T wak, T wbk, const typename C2<T>::type* s_ratp,
+                                            const unsigned char* s_rows,
+                                            typename C2<T>::type* y, int rb0, int rlen, int yb,
                                             bool colok, int lane, const T* br, const T* bi) {
   typedef SmallProp<PS, PA, T, MAXR> SP;
+  typedef typename C2<T>::type CT;
   typedef typename Mfma<T>::v4 V4;
-  constexpr int P = SP::P, NK = SP::NK, LW = SP::LW;
+  constexpr int P = SP::P, NG = SP::NG, LW = SP::LW;
+  const int kq = lane >> 4;
   for (int mt = 0; mt * 16 < rlen; ++mt) {
     const int arow = min(rb0 + mt * 16 + (lane & 15), P - 1);
-    const T* L = s_L + arow * LW;
-    T av[NK];
+    // ab[g]: L_a(g) L_b(kq) for g < PS, L_a(kq) L_b(4 + g - PS) above.
+    T ab[NG], Lc[PA];
+    if constexpr (LREG) {
+      T La[PS], Lb4[PA > 4 ? PA - 4 : 1];
+      const T* u = s_u + 3 * (int)s_rows[arow];
+      const T u0 = u[0], u1 = u[1];
+      T lak, lbk;
+      lagrange<PS, T>(u0, cheb.ts, cheb.ws, La);
+      lagrange<PA, T>(u[2], cheb.ta, cheb.wa, Lc);
+      lak = kq < PS ? lagrange_at<PS, T>(u0, cheb.ts, kq, wak) : (T)0;
+      lbk = kq < SP::PB ? lagrange_at<PA, T>(u1, cheb.ta, kq, wbk) : (T)0;
 #pragma unroll
-    for (int kk = 0; kk < NK; ++kk) {
-      const unsigned qi = qreg[kk];
-      av[kk] = L[qi & 0xff] * L[qi >> 8];
+      for (int e = 0; e < SP::NE; ++e)
+        Lb4[e] = lagrange_at<PA, T>(u1, cheb.ta, 4 + e, (T)cheb.wa[4 + e]);
+#pragma unroll
+      for (int g = 0; g < NG; ++g) ab[g] = g < PS ? La[g] * lbk : lak * Lb4[g < PS ? 0 : g - PS];
+    } else {
+      const T* L = s_L + arow * LW;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) ab[g] = L[kq * NG + g];
+#pragma unroll
+      for (int c = 0; c < PA; ++c) Lc[c] = L[4 * NG + c];
     }
     int pe[4];
-    T gc[4], gs[4];
+    CT rat[4];
 #pragma unroll
     for (int r4 = 0; r4 < 4; ++r4) {
       const int mm = mt * 16 + Mfma<T>::row(lane, r4);
-      const int pos = rb0 + (mm < rlen ? mm : 0);
-      pe[r4] = mm < rlen ? (int)s_rows[pos] : -1;
-      gc[r4] = s_rat[2 * pos];
-      gs[r4] = s_rat[2 * pos + 1];
+      pe[r4] = mm < rlen ? (int)s_rows[rb0 + mm] : -1;
+      rat[r4] = s_ratp[pe[r4] >= 0 ? pe[r4] : 0];
     }
     V4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
 #pragma unroll
-    for (int kk = 0; kk < NK; ++kk) {
-      accr = Mfma<T>::mma(av[kk], br[kk], accr);
-      acci = Mfma<T>::mma(av[kk], bi[kk], acci);
-    }
-    if (colok) {
-      T y0[4], y1[4];
+    for (int g = 0; g < NG; ++g)
 #pragma unroll
-      for (int r4 = 0; r4 < 4; ++r4) {
-        y0[r4] = (T)0;
-        y1[r4] = (T)0;
-        if (pe[r4] >= 0) {
-          y0[r4] = y[2 * (yb + pe[r4])];
-          y1[r4] = y[2 * (yb + pe[r4]) + 1];
-        }
+      for (int c = 0; c < PA; ++c) {
+        const T av = ab[g] * Lc[c];
+        accr = Mfma<T>::mma(av, br[g * PA + c], accr);
+        acci = Mfma<T>::mma(av, bi[g * PA + c], acci);
       }
+    if (colok) {
+      CT y0[4];
+#pragma unroll
+      for (int r4 = 0; r4 < 4; ++r4)
+        if (pe[r4] >= 0) y0[r4] = y[yb + pe[r4]];
 #pragma unroll
       for (int r4 = 0; r4 < 4; ++r4) {
         if (pe[r4] >= 0) {
-          y[2 * (yb + pe[r4])] = y0[r4] + accr[r4] * gc[r4] - acci[r4] * gs[r4];
-          y[2 * (yb + pe[r4]) + 1] = y1[r4] + accr[r4] * gs[r4] + acci[r4] * gc[r4];
+          CT v;
+          v.x = y0[r4].x + accr[r4] * rat[r4].x - acci[r4] * rat[r4].y;
+          v.y = y0[r4].y + accr[r4] * rat[r4].y + acci[r4] * rat[r4].x;
+          y[yb + pe[r4]] = v;
         }
       }
     }
@@ -1461,27 +1502,28 @@ __device__ __forceinline__ void small_tiles(const T* s_L, const T* s_rat,
 }
 
 template <int PS, int PA, typename T, int MAXR, int NWV>
-__global__ void __launch_bounds__(64 * NWV, 2)
+__global__ void __launch_bounds__(64 * NWV, sizeof(T) == 4 ? 3 : 2)
 prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc,
                   typename C2<T>::type* __restrict__ Vp) {
   typedef SmallProp<PS, PA, T, MAXR> SP;
   typedef typename C2<T>::type CT;
   typedef typename Mfma<T>::v4 V4;
-  constexpr int P = SP::P, NK = SP::NK, WB = SP::WB, NAMAX = SP::NAMAX, LW = SP::LW;
+  constexpr int P = SP::P, WB = SP::WB, NAMAX = SP::NAMAX, LW = SP::LW;
+  constexpr bool LREG = NWV == 1;           // factors in registers (one wave)
   static_assert(P <= 128, "two nodes per lane");
   // Shared per octant.
-  __shared__ T s_L[P * LW];                 // factors of the node at grouped position pos
-  __shared__ T s_rat[P * 2];                // ratio at pos
+  __shared__ __align__(16) T s_L[LREG ? 1 : P * LW];  // factors at grouped position pos
   __shared__ T s_u[P * 3];                  // local coordinates of node p
-  __shared__ T s_ratp[P * 2];               // ratio of node p
+  __shared__ CT s_ratp[P];                  // ratio of node p
   __shared__ int s_alpha[P];                // child cone of node p
   __shared__ unsigned char s_rows[P];       // node p at pos
-  __shared__ int s_rbeg[P + 1];
+  __shared__ unsigned char s_rbeg[P + 1];
   __shared__ int s_dist[P];                 // distinct child cones
   __shared__ int s_na;
   __shared__ unsigned s_om[NWV];            // octants with children, per wave
+  __shared__ unsigned char s_no[NWV][8];    // children per octant, per wave
   // Per wave.
-  __shared__ T s_y[NWV][WB * MAXR * P * 2];
+  __shared__ CT s_y[NWV][WB * MAXR * P];
   __shared__ int s_slot[NWV][WB];
   __shared__ int s_ch[NWV][8][WB];          // children per octant, compacted
   __shared__ unsigned char s_nl[NWV][8][WB]; // their box index in the wave's task
@@ -1507,7 +1549,7 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
   const double Hc = S.inst_H[inst];
   const double kappa = A.inst_kappa[inst];
   const unsigned long long lt = (1ull << lane) - 1ull;
-  T* const y = s_y[wave];
+  CT* const y = s_y[wave];
 
   // The wave's boxes and their children, compacted per octant.
   int box = 0;
@@ -1519,8 +1561,7 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
   int ch[8];
 #pragma unroll
   for (int o = 0; o < 8; ++o) ch[o] = lane < nbw ? Q.child[8 * (int64_t)box + o] : -1;
-  for (int i = lane; i < WB * MAXR * P * 2; i += 64) y[i] = (T)0;
-  int nos[8];
+  for (int i = lane; i < WB * MAXR * P; i += 64) y[i] = CT{(T)0, (T)0};
   unsigned om = 0;
 #pragma unroll
   for (int o = 0; o < 8; ++o) {
@@ -1530,25 +1571,18 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
       s_ch[wave][o][pos] = ch[o];
       s_nl[wave][o][pos] = (unsigned char)lane;
     }
-    nos[o] = __popcll(m);
+    if (lane == 0) s_no[wave][o] = (unsigned char)__popcll(m);
     if (m) om |= 1u << o;
   }
   if (lane == 0) s_om[wave] = om;
-  // Per lane: for each k-step, the offsets of (L_a L_b) and L_c of its node
-  // q in a row of s_L (the zero slot for q >= P).
-  unsigned qreg[NK];
-#pragma unroll
-  for (int kk = 0; kk < NK; ++kk) {
-    const int q = SP::qnode(kk, lane >> 4);
-    qreg[kk] = q < P ? (unsigned)(q / PA) | ((unsigned)(PS * PA + q % PA) << 8)
-                     : (unsigned)(LW - 1) | ((unsigned)(LW - 1) << 8);
-  }
   __syncthreads();
   unsigned omall = 0;
 #pragma unroll
   for (int w = 0; w < NWV; ++w) omall |= s_om[w];
 
   const int col = lane & 15, kq = lane >> 4;
+  const T wak = kq < PS ? (T)A.cheb.ws[kq] : (T)0;
+  const T wbk = kq < SP::PB ? (T)A.cheb.wa[kq] : (T)0;
 #pragma unroll 1
   for (int o = 0; o < 8; ++o) {
     if (!((omall >> o) & 1u)) continue;  // uniform across the block
@@ -1577,8 +1611,7 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
       T gcv, gsv;
       expi<T>(kappa * (cr.r - rj), gcv, gsv);
       const T amp = (T)(rj / cr.r);
-      s_ratp[2 * p] = gcv * amp;
-      s_ratp[2 * p + 1] = gsv * amp;
+      s_ratp[p] = CT{gcv * amp, gsv * amp};
     }
     __syncthreads();
     // Distinct child cones and the nodes grouped by child cone (wave 0,
@@ -1614,25 +1647,28 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
     }
     __syncthreads();
     const int na = s_na;
-    const int no = nos[o];
-    // Factors in grouped order (block); child cone slots of the wave's
-    // children.
-    for (int pos = tid; pos < P; pos += 64 * NWV) {
-      const int p = s_rows[pos];
-      T La[PS], Lb[PA], Lc[PA];
-      lagrange<PS, T>(s_u[3 * p], A.cheb.ts, A.cheb.ws, La);
-      lagrange<PA, T>(s_u[3 * p + 1], A.cheb.ta, A.cheb.wa, Lb);
-      lagrange<PA, T>(s_u[3 * p + 2], A.cheb.ta, A.cheb.wa, Lc);
-      T* L = s_L + pos * LW;
+    const int no = s_no[wave][o];
+    // Factors in grouped order (several waves); child cone slots of the
+    // wave's children.
+    if constexpr (!LREG) {
+      for (int pos = tid; pos < P; pos += 64 * NWV) {
+        const int p = s_rows[pos];
+        T La[PS], Lb[PA], Lc[PA];
+        lagrange<PS, T>(s_u[3 * p], A.cheb.ts, A.cheb.ws, La);
+        lagrange<PA, T>(s_u[3 * p + 1], A.cheb.ta, A.cheb.wa, Lb);
+        lagrange<PA, T>(s_u[3 * p + 2], A.cheb.ta, A.cheb.wa, Lc);
+        T* L = s_L + pos * LW;
 #pragma unroll
-      for (int a = 0; a < PS; ++a)
+        for (int gg = 0; gg < SP::NG; ++gg)
 #pragma unroll
-        for (int b = 0; b < PA; ++b) L[a * PA + b] = La[a] * Lb[b];
+          for (int j = 0; j < 4; ++j) {
+            int a, b;
+            const bool ok = SP::slot_ab(gg, j, a, b);
+            L[j * SP::NG + gg] = ok ? La[a] * Lb[b] : (T)0;
+          }
 #pragma unroll
-      for (int c = 0; c < PA; ++c) L[PS * PA + c] = Lc[c];
-      L[LW - 1] = (T)0;
-      s_rat[2 * pos] = s_ratp[2 * p];
-      s_rat[2 * pos + 1] = s_ratp[2 * p + 1];
+        for (int c = 0; c < PA; ++c) L[4 * SP::NG + c] = Lc[c];
+      }
     }
     {
       const int nac = min(na, NAMAX);
@@ -1665,10 +1701,10 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
         LIVE ? Vc + ((int64_t)(cs_ >= 0 ? cs_ : 0) * nrhs + r) * P : Vc, kq, BR, BI);      \
   } while (0)
 #define IFGF_SMALL_TILES(KK, BR, BI)                                                      \
-  small_tiles<PS, PA, T, MAXR>(s_L, s_rat, s_rows, y, qreg, s_rbeg[KK],                    \
-                               s_rbeg[(KK) + 1] - s_rbeg[KK], yb, colok, lane, BR, BI)
+  small_tiles<PS, PA, T, MAXR, LREG>(s_L, s_u, A.cheb, wak, wbk, s_ratp, s_rows, y, s_rbeg[KK], \
+                                     s_rbeg[(KK) + 1] - s_rbeg[KK], yb, colok, lane, BR, BI)
       for (int k = 0; k < na; ++k) {
-        T br[NK], bi[NK];
+        T br[SP::NK], bi[SP::NK];
         IFGF_SMALL_LOAD(k, true, br, bi);
         IFGF_SMALL_TILES(k, br, bi);
       }
@@ -1682,10 +1718,7 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
     const int n = i / (nrhs * P);
     const int rem = i - n * (nrhs * P);
     const int r = rem / P, p = rem - (rem / P) * P;
-    CT v;
-    v.x = y[2 * ((n * MAXR + r) * P + p)];
-    v.y = y[2 * ((n * MAXR + r) * P + p) + 1];
-    Vp[((int64_t)s_slot[wave][n] * nrhs + r) * P + p] = v;
+    Vp[((int64_t)s_slot[wave][n] * nrhs + r) * P + p] = y[(n * MAXR + r) * P + p];
   }
 }
 
