@@ -1425,109 +1425,115 @@ __device__ __forceinline__ void small_load_b(const typename C2<T>::type* __restr
   }
 }
 
-// Every M-tile of one child cone (rows rb0 .. rb0 + rlen - 1 of the
-// octant's grouping) times the B tile, added with the ratio into the
-// wave's accumulators y.  LREG: factors evaluated from s_u (node order)
+// One M-tile (rows rb .. rb + rlen - 1 of the octant's grouping, rlen <= 16,
+// all of one child cone) times the lane's B values, added with the ratio
+// into the accumulators y.  LREG: factors evaluated from s_u (node order)
 // instead of read from s_L (grouped order); wak, wbk are the weights of
 // L_a(kq), L_b(kq).
 template <int PS, int PA, typename T, int MAXR, bool LREG>
-__device__ __forceinline__ void small_tiles(const T* s_L, const T* s_u, const ChebConst& cheb,
-                                            T wak, T wbk, const typename C2<T>::type* s_ratp,
-                                            const unsigned char* s_rows,
-                                            typename C2<T>::type* y, int rb0, int rlen, int yb,
-                                            bool colok, int lane, const T* br, const T* bi) {
+__device__ __forceinline__ void small_tile(const T* s_L, const T* s_u, const ChebConst& cheb,
+                                           T wak, T wbk, const typename C2<T>::type* s_ratp,
+                                           const unsigned char* s_rows,
+                                           typename C2<T>::type* y, int rb, int rlen, int yb,
+                                           bool colok, int lane, const T* br, const T* bi) {
   typedef SmallProp<PS, PA, T, MAXR> SP;
   typedef typename C2<T>::type CT;
   typedef typename Mfma<T>::v4 V4;
   constexpr int P = SP::P, NG = SP::NG, LW = SP::LW;
   const int kq = lane >> 4;
-  for (int mt = 0; mt * 16 < rlen; ++mt) {
-    const int arow = min(rb0 + mt * 16 + (lane & 15), P - 1);
-    // ab[g]: L_a(g) L_b(kq) for g < PS, L_a(kq) L_b(4 + g - PS) above.
-    T ab[NG], Lc[PA];
-    if constexpr (LREG) {
-      T La[PS], Lb4[PA > 4 ? PA - 4 : 1];
-      const T* u = s_u + 3 * (int)s_rows[arow];
-      const T u0 = u[0], u1 = u[1];
-      T lak, lbk;
-      lagrange<PS, T>(u0, cheb.ts, cheb.ws, La);
-      lagrange<PA, T>(u[2], cheb.ta, cheb.wa, Lc);
-      lak = kq < PS ? lagrange_at<PS, T>(u0, cheb.ts, kq, wak) : (T)0;
-      lbk = kq < SP::PB ? lagrange_at<PA, T>(u1, cheb.ta, kq, wbk) : (T)0;
+  const int arow = min(rb + (lane & 15), P - 1);
+  // ab[g]: L_a(g) L_b(kq) for g < PS, L_a(kq) L_b(4 + g - PS) above.
+  T ab[NG], Lc[PA];
+  if constexpr (LREG) {
+    T La[PS], Lb4[PA > 4 ? PA - 4 : 1];
+    const T* u = s_u + 3 * (int)s_rows[arow];
+    const T u0 = u[0], u1 = u[1];
+    T lak, lbk;
+    lagrange<PS, T>(u0, cheb.ts, cheb.ws, La);
+    lagrange<PA, T>(u[2], cheb.ta, cheb.wa, Lc);
+    lak = kq < PS ? lagrange_at<PS, T>(u0, cheb.ts, kq, wak) : (T)0;
+    lbk = kq < SP::PB ? lagrange_at<PA, T>(u1, cheb.ta, kq, wbk) : (T)0;
 #pragma unroll
-      for (int e = 0; e < SP::NE; ++e)
-        Lb4[e] = lagrange_at<PA, T>(u1, cheb.ta, 4 + e, (T)cheb.wa[4 + e]);
+    for (int e = 0; e < SP::NE; ++e)
+      Lb4[e] = lagrange_at<PA, T>(u1, cheb.ta, 4 + e, (T)cheb.wa[4 + e]);
 #pragma unroll
-      for (int g = 0; g < NG; ++g) ab[g] = g < PS ? La[g] * lbk : lak * Lb4[g < PS ? 0 : g - PS];
-    } else {
-      const T* L = s_L + arow * LW;
+    for (int g = 0; g < NG; ++g) ab[g] = g < PS ? La[g] * lbk : lak * Lb4[g < PS ? 0 : g - PS];
+  } else {
+    const T* L = s_L + arow * LW;
 #pragma unroll
-      for (int g = 0; g < NG; ++g) ab[g] = L[kq * NG + g];
+    for (int g = 0; g < NG; ++g) ab[g] = L[kq * NG + g];
 #pragma unroll
-      for (int c = 0; c < PA; ++c) Lc[c] = L[4 * NG + c];
+    for (int c = 0; c < PA; ++c) Lc[c] = L[4 * NG + c];
+  }
+  int pe[4];
+  CT rat[4];
+#pragma unroll
+  for (int r4 = 0; r4 < 4; ++r4) {
+    const int mm = Mfma<T>::row(lane, r4);
+    pe[r4] = mm < rlen ? (int)s_rows[rb + mm] : -1;
+    rat[r4] = s_ratp[pe[r4] >= 0 ? pe[r4] : 0];
+  }
+  V4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+#pragma unroll
+  for (int g = 0; g < NG; ++g)
+#pragma unroll
+    for (int c = 0; c < PA; ++c) {
+      const T av = ab[g] * Lc[c];
+      accr = Mfma<T>::mma(av, br[g * PA + c], accr);
+      acci = Mfma<T>::mma(av, bi[g * PA + c], acci);
     }
-    int pe[4];
-    CT rat[4];
+  if (colok) {
+    CT y0[4];
+#pragma unroll
+    for (int r4 = 0; r4 < 4; ++r4)
+      if (pe[r4] >= 0) y0[r4] = y[yb + pe[r4]];
 #pragma unroll
     for (int r4 = 0; r4 < 4; ++r4) {
-      const int mm = mt * 16 + Mfma<T>::row(lane, r4);
-      pe[r4] = mm < rlen ? (int)s_rows[rb0 + mm] : -1;
-      rat[r4] = s_ratp[pe[r4] >= 0 ? pe[r4] : 0];
-    }
-    V4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
-#pragma unroll
-    for (int g = 0; g < NG; ++g)
-#pragma unroll
-      for (int c = 0; c < PA; ++c) {
-        const T av = ab[g] * Lc[c];
-        accr = Mfma<T>::mma(av, br[g * PA + c], accr);
-        acci = Mfma<T>::mma(av, bi[g * PA + c], acci);
-      }
-    if (colok) {
-      CT y0[4];
-#pragma unroll
-      for (int r4 = 0; r4 < 4; ++r4)
-        if (pe[r4] >= 0) y0[r4] = y[yb + pe[r4]];
-#pragma unroll
-      for (int r4 = 0; r4 < 4; ++r4) {
-        if (pe[r4] >= 0) {
-          CT v;
-          v.x = y0[r4].x + accr[r4] * rat[r4].x - acci[r4] * rat[r4].y;
-          v.y = y0[r4].y + accr[r4] * rat[r4].y + acci[r4] * rat[r4].x;
-          y[yb + pe[r4]] = v;
-        }
+      if (pe[r4] >= 0) {
+        CT v;
+        v.x = y0[r4].x + accr[r4] * rat[r4].x - acci[r4] * rat[r4].y;
+        v.y = y0[r4].y + accr[r4] * rat[r4].y + acci[r4] * rat[r4].x;
+        y[yb + pe[r4]] = v;
       }
     }
   }
 }
 
+// The children of the block's boxes are compacted per octant across the
+// whole block, so an N-tile holds 16 (child, rhs) columns of any of its
+// waves' boxes; the octant's work items (N-tile, M-tile) are cut into NWV
+// contiguous ranges, one per wave.  Within an octant every (box, node) is
+// written by exactly one item (M-tiles of different child cones hold
+// different nodes), so the block-wide accumulators need no atomics.
 template <int PS, int PA, typename T, int MAXR, int NWV>
 __global__ void __launch_bounds__(64 * NWV, sizeof(T) == 4 ? 3 : 2)
 prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc,
                   typename C2<T>::type* __restrict__ Vp) {
   typedef SmallProp<PS, PA, T, MAXR> SP;
   typedef typename C2<T>::type CT;
-  typedef typename Mfma<T>::v4 V4;
-  constexpr int P = SP::P, WB = SP::WB, NAMAX = SP::NAMAX, LW = SP::LW;
+  constexpr int P = SP::P, NAMAX = SP::NAMAX, LW = SP::LW;
+  constexpr int NB = NWV * SP::WB;          // boxes per block
   constexpr bool LREG = NWV == 1;           // factors in registers (one wave)
   static_assert(P <= 128, "two nodes per lane");
+  static_assert(NB <= 64, "one lane per box");
   // Shared per octant.
   __shared__ __align__(16) T s_L[LREG ? 1 : P * LW];  // factors at grouped position pos
   __shared__ T s_u[P * 3];                  // local coordinates of node p
   __shared__ CT s_ratp[P];                  // ratio of node p
   __shared__ int s_alpha[P];                // child cone of node p
   __shared__ unsigned char s_rows[P];       // node p at pos
-  __shared__ unsigned char s_rbeg[P + 1];
+  __shared__ unsigned char s_rbeg[P + 1];   // first pos of each child cone
   __shared__ int s_dist[P];                 // distinct child cones
-  __shared__ int s_na;
-  __shared__ unsigned s_om[NWV];            // octants with children, per wave
-  __shared__ unsigned char s_no[NWV][8];    // children per octant, per wave
-  // Per wave.
-  __shared__ CT s_y[NWV][WB * MAXR * P];
-  __shared__ int s_slot[NWV][WB];
-  __shared__ int s_ch[NWV][8][WB];          // children per octant, compacted
-  __shared__ unsigned char s_nl[NWV][8][WB]; // their box index in the wave's task
-  __shared__ int s_cs[NWV][WB * NAMAX];     // child cone slots of the current octant
+  __shared__ unsigned char s_mk[NWV > 1 ? P : 1];  // M-tile j: child cone, first pos
+  __shared__ unsigned char s_mr[NWV > 1 ? P : 1];
+  __shared__ int s_na, s_nm;
+  // Per block.
+  __shared__ CT s_y[NB * MAXR * P];
+  __shared__ int s_slot[NB];
+  __shared__ int s_ch[8][NB];               // children per octant, compacted
+  __shared__ unsigned char s_nl[8][NB];     // their box index in the chunk
+  __shared__ unsigned char s_no[8];         // children per octant
+  __shared__ int s_cs[NB * NAMAX];          // child cone slots of the current octant
 
   const StepDev& S = A.step[l];
   const StepDev& Q = A.step[l + 1];
@@ -1536,7 +1542,7 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
   const int64_t* cstart = NWV == 1 ? Q.schunk_start : Q.mchunk_start;
   const int* clen = NWV == 1 ? Q.schunk_len : Q.mchunk_len;
   const int64_t g0 = cstart[blockIdx.x];
-  const int nbw = max(0, min(WB, clen[blockIdx.x] - wave * WB));  // boxes of this wave
+  const int nb = clen[blockIdx.x];          // boxes of this chunk, <= NB
   const unsigned long long key0 = Q.cone_key[Q.gslot[g0]];
   const int64_t j0 = (int64_t)(key0 / (unsigned long long)Q.ngrid);
   const int64_t g = (int64_t)(key0 - (unsigned long long)j0 * Q.ngrid);
@@ -1549,43 +1555,39 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
   const double Hc = S.inst_H[inst];
   const double kappa = A.inst_kappa[inst];
   const unsigned long long lt = (1ull << lane) - 1ull;
-  CT* const y = s_y[wave];
 
-  // The wave's boxes and their children, compacted per octant.
-  int box = 0;
-  if (lane < nbw) {
-    const int slot = Q.gslot[g0 + wave * WB + lane];
-    s_slot[wave][lane] = slot;
-    box = (int)(Q.cone_key[slot] / (unsigned long long)Q.ngrid);
-  }
-  int ch[8];
-#pragma unroll
-  for (int o = 0; o < 8; ++o) ch[o] = lane < nbw ? Q.child[8 * (int64_t)box + o] : -1;
-  for (int i = lane; i < WB * MAXR * P; i += 64) y[i] = CT{(T)0, (T)0};
-  unsigned om = 0;
-#pragma unroll
-  for (int o = 0; o < 8; ++o) {
-    const unsigned long long m = __ballot(ch[o] >= 0);
-    if (ch[o] >= 0) {
-      const int pos = __popcll(m & lt);
-      s_ch[wave][o][pos] = ch[o];
-      s_nl[wave][o][pos] = (unsigned char)lane;
+  // The chunk's boxes and their children, compacted per octant (wave 0).
+  if (wave == 0) {
+    int box = 0;
+    if (lane < nb) {
+      const int slot = Q.gslot[g0 + lane];
+      s_slot[lane] = slot;
+      box = (int)(Q.cone_key[slot] / (unsigned long long)Q.ngrid);
     }
-    if (lane == 0) s_no[wave][o] = (unsigned char)__popcll(m);
-    if (m) om |= 1u << o;
-  }
-  if (lane == 0) s_om[wave] = om;
-  __syncthreads();
-  unsigned omall = 0;
+    int ch[8];  // all eight loads in flight before the first ballot
 #pragma unroll
-  for (int w = 0; w < NWV; ++w) omall |= s_om[w];
+    for (int o = 0; o < 8; ++o) ch[o] = lane < nb ? Q.child[8 * (int64_t)box + o] : -1;
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      const unsigned long long m = __ballot(ch[o] >= 0);
+      if (ch[o] >= 0) {
+        const int pos = __popcll(m & lt);
+        s_ch[o][pos] = ch[o];
+        s_nl[o][pos] = (unsigned char)lane;
+      }
+      if (lane == 0) s_no[o] = (unsigned char)__popcll(m);
+    }
+  }
+  for (int i = tid; i < NB * MAXR * P; i += 64 * NWV) s_y[i] = CT{(T)0, (T)0};
+  __syncthreads();
 
   const int col = lane & 15, kq = lane >> 4;
   const T wak = kq < PS ? (T)A.cheb.ws[kq] : (T)0;
   const T wbk = kq < SP::PB ? (T)A.cheb.wa[kq] : (T)0;
 #pragma unroll 1
   for (int o = 0; o < 8; ++o) {
-    if (!((omall >> o) & 1u)) continue;  // uniform across the block
+    const int no = s_no[o];
+    if (no == 0) continue;  // uniform across the block
     // Node geometry of octant o.
     for (int p = tid; p < P; p += 64 * NWV) {
       const int a = p / (PA * PA), bb = (p / PA) % PA, cc = p % PA;
@@ -1614,8 +1616,9 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
       s_ratp[p] = CT{gcv * amp, gsv * amp};
     }
     __syncthreads();
-    // Distinct child cones and the nodes grouped by child cone (wave 0,
-    // ballots; lane holds nodes lane and lane + 64).
+    // Distinct child cones, the nodes grouped by child cone and the M-tiles
+    // of every child cone (wave 0, ballots; lane holds nodes lane and
+    // lane + 64).
     if (wave == 0) {
       const bool has0 = lane < P, has1 = lane + 64 < P;
       const int a0 = has0 ? s_alpha[lane] : -1;
@@ -1632,24 +1635,31 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
         if (lane == 0) s_dist[na] = lead;
         ++na;
       }
-      int base = 0;
+      int base = 0, nm = 0;
       for (int k = 0; k < na; ++k) {
         const unsigned long long m0 = __ballot(has0 && k0 == k), m1 = __ballot(has1 && k1 == k);
         if (has0 && k0 == k) s_rows[base + __popcll(m0 & lt)] = (unsigned char)lane;
         if (has1 && k1 == k) s_rows[base + __popcll(m0) + __popcll(m1 & lt)] = (unsigned char)(lane + 64);
+        const int rlen = __popcll(m0) + __popcll(m1);
+        const int ntk = (rlen + 15) >> 4;
+        if (NWV > 1 && lane < ntk) {  // one wave: its range starts at M-tile 0
+          s_mk[nm + lane] = (unsigned char)k;
+          s_mr[nm + lane] = (unsigned char)(base + 16 * lane);
+        }
         if (lane == 0) s_rbeg[k] = base;
-        base += __popcll(m0) + __popcll(m1);
+        base += rlen;
+        nm += ntk;
       }
       if (lane == 0) {
         s_rbeg[na] = base;
         s_na = na;
+        s_nm = nm;
       }
     }
     __syncthreads();
-    const int na = s_na;
-    const int no = s_no[wave][o];
+    const int na = s_na, nm = s_nm;
     // Factors in grouped order (several waves); child cone slots of the
-    // wave's children.
+    // block's children.
     if constexpr (!LREG) {
       for (int pos = tid; pos < P; pos += 64 * NWV) {
         const int p = s_rows[pos];
@@ -1672,53 +1682,68 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
     }
     {
       const int nac = min(na, NAMAX);
-      for (int e = lane; e < no * nac; e += 64) {
+      for (int e = tid; e < no * nac; e += 64 * NWV) {
         const int k = e / no, n = e - k * no;
-        const int cs = cone_lookup(S, (unsigned long long)s_ch[wave][o][n] * S.ngrid + s_dist[k]);
+        const int cs = cone_lookup(S, (unsigned long long)s_ch[o][n] * S.ngrid + s_dist[k]);
         if (cs < 0) atomicOr(A.err, 1);
-        s_cs[wave][n * NAMAX + k] = cs;
+        s_cs[n * NAMAX + k] = cs;
       }
     }
     __syncthreads();
-    if (no > 0) {
-      const int ncols = no * nrhs;
-      const bool colok = col < ncols;
-      const int n0 = col / nrhs;
-      const int nn = colok ? n0 : 0;
-      const int r = colok ? col - n0 * nrhs : 0;
-      const int yb = colok ? ((int)s_nl[wave][o][nn] * MAXR + r) * P : 0;
-      // B tile of child cone KK (lane: column col, nodes of lane group kq).
-#define IFGF_SMALL_LOAD(KK, LIVE, BR, BI)                                                  \
-  do {                                                                                     \
-    int cs_;                                                                               \
-    if ((KK) < NAMAX) {                                                                    \
-      cs_ = s_cs[wave][nn * NAMAX + (KK)];                                                 \
-    } else {                                                                               \
-      cs_ = cone_lookup(S, (unsigned long long)s_ch[wave][o][nn] * S.ngrid + s_dist[KK]);  \
-      if (cs_ < 0) atomicOr(A.err, 1);                                                     \
-    }                                                                                      \
-    small_load_b<PS, PA, T, MAXR>(                                                         \
-        LIVE ? Vc + ((int64_t)(cs_ >= 0 ? cs_ : 0) * nrhs + r) * P : Vc, kq, BR, BI);      \
-  } while (0)
-#define IFGF_SMALL_TILES(KK, BR, BI)                                                      \
-  small_tiles<PS, PA, T, MAXR, LREG>(s_L, s_u, A.cheb, wak, wbk, s_ratp, s_rows, y, s_rbeg[KK], \
-                                     s_rbeg[(KK) + 1] - s_rbeg[KK], yb, colok, lane, BR, BI)
-      for (int k = 0; k < na; ++k) {
-        T br[SP::NK], bi[SP::NK];
-        IFGF_SMALL_LOAD(k, true, br, bi);
-        IFGF_SMALL_TILES(k, br, bi);
+    // Work items (N-tile nt, M-tile j), nt major; wave w takes a contiguous
+    // range and walks it unit by unit, a unit being the M-tiles of one
+    // (nt, child cone k) in the range, with one B load per unit.
+    const int ncols = no * nrhs;
+    const int nit = ((ncols + 15) >> 4) * nm;
+    const int i0 = (int)(((int64_t)nit * wave) / NWV), i1 = (int)(((int64_t)nit * (wave + 1)) / NWV);
+    int nt = i0 / nm, k = 0, rb = 0, rend = 0;
+    if (i0 < i1) {
+      if constexpr (NWV > 1) {
+        const int j = i0 - nt * nm;
+        k = s_mk[j];
+        rb = s_mr[j];
       }
-#undef IFGF_SMALL_LOAD
-#undef IFGF_SMALL_TILES
+      rend = s_rbeg[k + 1];
+    }
+    int item = i0;
+    while (item < i1) {
+      const int c = nt * 16 + col;
+      const bool colok = c < ncols;
+      const int n0 = !colok ? 0 : MAXR == 1 ? c : c / nrhs;
+      const int r = !colok || MAXR == 1 ? 0 : c - n0 * nrhs;
+      const int yb = colok ? ((int)s_nl[o][n0] * MAXR + r) * P : 0;
+      int cs;
+      if (k < NAMAX) {
+        cs = s_cs[n0 * NAMAX + k];
+      } else {
+        cs = cone_lookup(S, (unsigned long long)s_ch[o][n0] * S.ngrid + s_dist[k]);
+        if (cs < 0) atomicOr(A.err, 1);
+      }
+      T br[SP::NK], bi[SP::NK];
+      small_load_b<PS, PA, T, MAXR>(Vc + ((int64_t)(cs >= 0 ? cs : 0) * nrhs + r) * P, kq, br, bi);
+      do {
+        small_tile<PS, PA, T, MAXR, LREG>(s_L, s_u, A.cheb, wak, wbk, s_ratp, s_rows, s_y, rb,
+                                          min(16, rend - rb), yb, colok, lane, br, bi);
+        ++item;
+        rb += 16;
+      } while (item < i1 && rb < rend);
+      if (rb >= rend) {  // next child cone, or the first of the next N-tile
+        if (++k == na) {
+          k = 0;
+          ++nt;
+        }
+        rb = s_rbeg[k];
+        rend = s_rbeg[k + 1];
+      }
     }
     __syncthreads();
   }
-  // Write the parent cones of the wave's boxes.
-  for (int i = lane; i < nbw * nrhs * P; i += 64) {
+  // Write the parent cones of the chunk's boxes.
+  for (int i = tid; i < nb * nrhs * P; i += 64 * NWV) {
     const int n = i / (nrhs * P);
     const int rem = i - n * (nrhs * P);
     const int r = rem / P, p = rem - (rem / P) * P;
-    Vp[((int64_t)s_slot[wave][n] * nrhs + r) * P + p] = y[(n * MAXR + r) * P + p];
+    Vp[((int64_t)s_slot[n] * nrhs + r) * P + p] = s_y[(n * MAXR + r) * P + p];
   }
 }
 

@@ -267,6 +267,24 @@ def test_kernel_variants_match_oracle(prop, lookup, precision, tol):
     assert relerr(g[0], o) <= tol
 
 
+@pytest.mark.parametrize("n_rhs", [1, 4])
+def test_wave_task_kernels_match_per_node_at_scale(n_rhs):
+    """At N = 60,000 parent cone indices are shared by tens to hundreds of
+    boxes, so the four-wave kernel's octants span several N-tiles split over
+    its waves; the one- and four-wave kernels agree with the per-node kernel
+    (itself pinned to the oracle) to FP64 rounding."""
+    n = 60000
+    p = W.fibonacci_sphere(n)
+    k = W.kappa_sphere_10ppw(n)
+    a = W.densities(n, n_rhs, 38)
+    say("wave-task vs per-node", n, n_rhs)
+    ref, _ = run_gpu(p, a, k, prop_kernel="node")
+    for prop, mode in (("small", 3), ("medium", 4)):
+        g, info = run_gpu(p, a, k, prop_kernel=prop)
+        assert mode in info["prop_mode"], (prop, info["prop_mode"])
+        assert relerr(g, ref) <= 1e-12, prop
+
+
 @pytest.mark.parametrize("prop", ["grouped", "small", "medium"])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
 def test_graph_replays_match_eager(precision, tol, prop):
