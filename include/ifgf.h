@@ -68,12 +68,11 @@ typedef struct ifgf_opts {
   int device;       /* HIP device ordinal; -1 uses the current device */
   void* stream;     /* hipStream_t used by ifgf_apply; NULL = null stream */
   int prop_kernel;  /* propagation kernel per level: 0 chooses by the mean
-                       number of boxes sharing a parent cone index (>= 160:
-                       matrix-core blocks; >= 32: four-wave matrix-core
-                       tasks; >= 4: one-wave matrix-core tasks; else
-                       per-node), 1 forces the per-node form, 2 the
-                       matrix-core block form, 3 the one-wave task form,
-                       4 the four-wave task form */
+                       number of boxes sharing a parent cone index (>= 32:
+                       four-wave matrix-core tasks; >= 4: one-wave
+                       matrix-core tasks; else per-node), 1 forces the
+                       per-node form, 2 the matrix-core block form, 3 the
+                       one-wave task form, 4 the four-wave task form */
   int lookup;       /* cone look-up: 0 dense tables where a level's table
                        (boxes x cone grid) has <= 2^28 entries, hash tables
                        elsewhere; 1 hash tables everywhere */

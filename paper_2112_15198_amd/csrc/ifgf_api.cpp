@@ -384,14 +384,14 @@ static void build_device(ifgf_plan_s* P) {
           }
           mlen.back() += 1;
         }
-        // Without the autotuner: the block kernel where many boxes share a
-        // parent cone index (>= 160 on average), the four-wave task kernel
-        // where some do (>= 32), the one-wave task kernel where a few do
-        // (>= 4), the per-node kernel otherwise.
+        // Without the autotuner: the four-wave task kernel where many boxes
+        // share a parent cone index (>= 32 on average), the one-wave task
+        // kernel where a few do (>= 4), the per-node kernel otherwise; the
+        // block kernel only when asked for.
         double mean = (double)count / (double)std::max<int64_t>(groups, 1);
         int mode = P->opts.prop_kernel;
         if (PP <= kMfmaMaxP) {
-          if (mode == 2 || (mode == 0 && mean >= 160.0))
+          if (mode == 2)
             D.prop_grouped = kPropGrouped;
           else if (mode == 4 || (mode == 0 && mean >= 32.0))
             D.prop_grouped = kPropMedium;
