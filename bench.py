@@ -15,6 +15,8 @@ Prints one JSON line:
   value      = N^2 * n_rhs / t (FP32-mixed), t = mean apply time (sum of
                N_i^2 over the instances of a batched workload)
   fp64       = the same for the FP64 path
+  bf16x3     = the same for FP32-mixed with the propagation product on BF16
+               matrix cores in three-term split form (not the headline)
   rel_err    = relative l2 error against the FP64 direct sum on 4,096
                sampled targets (eq. errorcomputation of the paper)
   roofline   = the dominant kernel: algorithmic FLOP per launch over its
@@ -42,8 +44,10 @@ if ROOT not in sys.path:
 METRIC = "IFGF matvec ms & N^2/t at rel-err<=1e-4 vs FP64 direct: FP32-mixed vs FP64"
 
 # MI355X published dense peaks: FP32 157.3 TFLOP/s, FP64 78.6 (vector and
-# matrix cores alike).
-PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
+# matrix cores alike); BF16 matrix cores 2,500, of which a three-term split
+# product uses three per FP32-equivalent product.
+PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "bf16x3": 157.3}
+PEAK_BF16X3_PRODUCT = 2500.0 / 3
 
 
 def flops_per_eval(P):
@@ -109,7 +113,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="sphere_321k")
-    ap.add_argument("--precision", choices=["both", "fp32", "fp64"], default="both")
+    ap.add_argument("--precision", choices=["all", "both", "fp32", "fp64", "bf16x3"],
+                    default="all",
+                    help="all: FP32-mixed (headline), FP64 and FP32 with the three-term BF16 "
+                         "propagation product; both: the first two")
     ap.add_argument("--samples-batch", type=int, default=256,
                     help="error-check targets per instance of a batched workload")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -145,7 +152,8 @@ def main():
     dens = np.concatenate([x.dens for x in insts], axis=1)
     p_s, p_ang, grid = 3, 5, (2, 4, 8)
     P = p_s * p_ang * p_ang
-    precs = ["fp32", "fp64"] if args.precision == "both" else [args.precision]
+    precs = {"all": ["fp32", "fp64", "bf16x3"], "both": ["fp32", "fp64"]}.get(
+        args.precision, [args.precision])
     res = {}
     for prec in precs:
         t0 = time.perf_counter()
@@ -159,7 +167,7 @@ def main():
         plan_s = time.perf_counter() - t0
         print(f"# {prec}: plan {plan_s:.2f} s (N={n}, D={pl.info()['D']})",
               file=sys.stderr, flush=True)
-        dt = torch.complex64 if prec == "fp32" else torch.complex128
+        dt = torch.complex128 if prec == "fp64" else torch.complex64
         a = torch.from_numpy(dens).to(dt).cuda()
         ms_eager, _ = time_applies(pl, a, args.steps, args.warmup, graph=False)
         print(f"# {prec}: eager {ms_eager:.3f} ms/apply", file=sys.stderr, flush=True)
@@ -177,7 +185,7 @@ def main():
         del a, out
         torch.cuda.empty_cache()
 
-    head = "fp32" if "fp32" in res else "fp64"
+    head = next(p for p in ("fp32", "bf16x3", "fp64") if p in res)
     R = res[head]
     ms = R["ms"]
     # Matvec-equivalents: one apply evaluates n_rhs operators.
@@ -211,7 +219,8 @@ def main():
         unit_txt = "near-field pairs"
     per_launch = flop / launches
     achieved = per_launch / (avg_ms * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[head]
+    peak = PEAK_BF16X3_PRODUCT if (head == "bf16x3" and dom == "propagation_small") \
+        else PEAK_TFLOPS[head]
     roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                 "traffic": measured_traffic(dom, args.workload, head),
@@ -232,22 +241,28 @@ def main():
                "geometry": ("unit-sphere" if "sphere" in args.workload else
                             "(1,1,0.25) spheroid") + " Fibonacci lattice"}
     cfg.update({"p_s": p_s, "p_ang": p_ang, "leaf_grid": list(grid), "n_rhs": n_rhs,
-                "D": info["D"], "precision": "fp32-mixed" if head == "fp32" else "fp64",
+                "D": info["D"], "precision": {"fp32": "fp32-mixed", "fp64": "fp64",
+                                              "bf16x3": "fp32-mixed, bf16x3 propagation"}[head],
                 "apply": "captured HIP graph"})
     line = {"metric": METRIC, "value": value, "unit": "N^2/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-            "dtype": "f32-mixed" if head == "fp32" else "f64", "data": "synthetic",
+            "dtype": {"fp32": "f32-mixed", "fp64": "f64", "bf16x3": "f32-mixed+bf16x3"}[head],
+            "data": "synthetic",
             "config": cfg,
             "plan_s": R["plan_s"], "ms_per_step_eager": R["ms_eager"],
             "prop_kernel_per_level": info["prop_mode"],
             "stages_ms": {k: round(v[0] / args.steps, 4) for k, v in st.items()},
             "roofline": roofline}
+    for other in ("fp64", "bf16x3"):
+        if other in res and head != other:
+            line[other] = {"ms_per_step": res[other]["ms"],
+                           "ms_per_step_eager": res[other]["ms_eager"],
+                           "value": n2 * n_rhs / (res[other]["ms"] * 1e-3),
+                           "prop_kernel_per_level": res[other]["info"]["prop_mode"],
+                           "stages_ms": {k: round(v[0] / args.steps, 4)
+                                         for k, v in res[other]["stages"].items()}}
     if "fp64" in res and head != "fp64":
-        line["fp64"] = {"ms_per_step": res["fp64"]["ms"], "ms_per_step_eager": res["fp64"]["ms_eager"],
-                        "value": n2 * n_rhs / (res["fp64"]["ms"] * 1e-3),
-                        "stages_ms": {k: round(v[0] / args.steps, 4)
-                                      for k, v in res["fp64"]["stages"].items()}}
         line["speedup_fp32_mixed_over_fp64"] = res["fp64"]["ms"] / ms
 
     if not args.no_cpu:
@@ -280,8 +295,9 @@ def main():
                        f"full-matvec time extrapolated pro rata"),
             "seconds": t_cpu}
         line["rel_err"] = errs[head]
-        if "fp64" in line:
-            line["fp64"]["rel_err"] = errs["fp64"]
+        for other in ("fp64", "bf16x3"):
+            if other in line:
+                line[other]["rel_err"] = errs[other]
     print(json.dumps(line), flush=True)
 
 

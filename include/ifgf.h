@@ -17,7 +17,8 @@
  *   - Points are FP64, N x 3 row-major, in HOST memory.  Densities and
  *     outputs are DEVICE pointers on the plan's GPU.
  *   - Complex numbers are interleaved (re, im): complex128 (two doubles) in
- *     IFGF_FP64 mode, complex64 (two floats) in IFGF_FP32_MIXED mode.
+ *     IFGF_FP64 mode, complex64 (two floats) in IFGF_FP32_MIXED and
+ *     IFGF_FP32_BF16X3 modes.
  *   - Densities and outputs are laid out [n_rhs][N] in the caller's point
  *     order (RHS-major, point index fastest).
  */
@@ -45,7 +46,7 @@ typedef enum {
                            consistency error; reported by ifgf_check) */
 } ifgf_status;
 
-typedef enum { IFGF_FP64 = 0, IFGF_FP32_MIXED = 1 } ifgf_precision;
+typedef enum { IFGF_FP64 = 0, IFGF_FP32_MIXED = 1, IFGF_FP32_BF16X3 = 2 } ifgf_precision;
 
 /* Options of a plan.  Obtain defaults with ifgf_default_opts(). */
 typedef struct ifgf_opts {
@@ -53,7 +54,14 @@ typedef struct ifgf_opts {
                        propagation and near field in FP32 complex; point and
                        box-centre geometry, cone selection, the phase
                        kappa*|x - x_c| (argument reduction) and the
-                       centred-factor ratio in FP64. */
+                       centred-factor ratio in FP64.  IFGF_FP32_BF16X3: as
+                       IFGF_FP32_MIXED, except that the wave-task
+                       propagation kernels take the interpolation product
+                       on BF16 matrix cores in three-term split form
+                       (x = bf16(x) + bf16(x - bf16(x)) for both operands,
+                       the low-by-low term dropped, FP32 accumulation;
+                       about 2^-16 relative error per product; an addition
+                       beyond the paper). */
   int n_rhs;        /* number of right-hand sides per apply, >= 1 */
   int leaf_grid[3]; /* cone-segment grid (n_s, n_theta, n_phi) at the leaf
                        level D; each level up doubles every dimension.
@@ -149,7 +157,7 @@ ifgf_status ifgf_plan_batched(ifgf_plan_t* plan, int n_inst,
 /* Evaluate out = A(densities) (eq. (field1)) on the plan's stream.
  * densities, out: device pointers, [n_rhs][N] interleaved complex of the
  * plan's precision (complex128 for IFGF_FP64, complex64 for
- * IFGF_FP32_MIXED); out is overwritten.  Asynchronous with respect to the
+ * IFGF_FP32_MIXED and IFGF_FP32_BF16X3); out is overwritten.  Asynchronous with respect to the
  * host; one apply at a time per plan (not re-entrant). */
 ifgf_status ifgf_apply(ifgf_plan_t plan, const void* densities, void* out);
 

@@ -109,7 +109,8 @@ struct ifgf_plan_s {
 
 static ifgf_status validate(int p_s, int p_ang, const ifgf_opts& o) {
   if (p_s < 1 || p_ang < 1) return fail(IFGF_EINVAL, "p_s and p_ang must be >= 1");
-  if (o.precision != IFGF_FP64 && o.precision != IFGF_FP32_MIXED)
+  if (o.precision != IFGF_FP64 && o.precision != IFGF_FP32_MIXED &&
+      o.precision != IFGF_FP32_BF16X3)
     return fail(IFGF_EINVAL, "unknown precision");
   if (o.n_rhs < 1) return fail(IFGF_EINVAL, "n_rhs must be >= 1");
   if (o.n_rhs > kMaxRhs) return fail(IFGF_EUNSUPPORTED, "n_rhs > 4 is not supported");

@@ -1425,17 +1425,51 @@ __device__ __forceinline__ void small_load_b(const typename C2<T>::type* __restr
   }
 }
 
+// Three-term BF16 form of the propagation product (an addition beyond the
+// paper): each FP32 operand x is split into x_hi = bf16(x) and
+// x_lo = bf16(x - x_hi) (round to nearest even), and A B is taken as
+// A_lo B_hi + A_hi B_lo + A_hi B_hi on v_mfma_f32_16x16x32_bf16 with FP32
+// accumulation; the dropped A_lo B_lo and the rounding of the low parts
+// leave a relative error of about 2^-16 per product.  A lane's K values keep
+// the k-step order of the FP32 form, eight per instruction (value v = 8 s + i,
+// zero from NK on); A and B share the (lane group, element) -> k pairing.
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+template <int NK>
+struct SplitB {
+  static constexpr int NS = (NK + 7) / 8;  // BF16 instructions per product
+  bf8v rh[NS], rl[NS], ih[NS], il[NS];    // Re and Im, high and low parts
+};
+
+template <int NK>
+__device__ __forceinline__ void split_b(const float* br, const float* bi, SplitB<NK>& sb) {
+#pragma unroll
+  for (int st = 0; st < SplitB<NK>::NS; ++st)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int v = 8 * st + i;
+      const float xr = v < NK ? br[v] : 0.f, xi = v < NK ? bi[v] : 0.f;
+      const __bf16 hr = (__bf16)xr, hi = (__bf16)xi;
+      sb.rh[st][i] = hr;
+      sb.rl[st][i] = (__bf16)(xr - (float)hr);
+      sb.ih[st][i] = hi;
+      sb.il[st][i] = (__bf16)(xi - (float)hi);
+    }
+}
+
 // One M-tile (rows rb .. rb + rlen - 1 of the octant's grouping, rlen <= 16,
 // all of one child cone) times the lane's B values, added with the ratio
 // into the accumulators y.  LREG: factors evaluated from s_u (node order)
 // instead of read from s_L (grouped order); wak, wbk are the weights of
-// L_a(kq), L_b(kq).
-template <int PS, int PA, typename T, int MAXR, bool LREG>
+// L_a(kq), L_b(kq).  SPLIT: the product in three-term BF16 form, B taken
+// from sb.
+template <int PS, int PA, typename T, int MAXR, bool LREG, bool SPLIT>
 __device__ __forceinline__ void small_tile(const T* s_L, const T* s_u, const ChebConst& cheb,
                                            T wak, T wbk, const typename C2<T>::type* s_ratp,
                                            const unsigned char* s_rows,
                                            typename C2<T>::type* y, int rb, int rlen, int yb,
-                                           bool colok, int lane, const T* br, const T* bi) {
+                                           bool colok, int lane, const T* br, const T* bi,
+                                           const SplitB<SmallProp<PS, PA, T, MAXR>::NK>& sb) {
   typedef SmallProp<PS, PA, T, MAXR> SP;
   typedef typename C2<T>::type CT;
   typedef typename Mfma<T>::v4 V4;
@@ -1474,14 +1508,37 @@ __device__ __forceinline__ void small_tile(const T* s_L, const T* s_u, const Che
     rat[r4] = s_ratp[pe[r4] >= 0 ? pe[r4] : 0];
   }
   V4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+  if constexpr (SPLIT) {
+    static_assert(sizeof(T) == 4, "three-term BF16 form of the FP32 product");
+    constexpr int NK = SP::NK;
 #pragma unroll
-  for (int g = 0; g < NG; ++g)
+    for (int st = 0; st < SplitB<NK>::NS; ++st) {
+      bf8v ah, al;
 #pragma unroll
-    for (int c = 0; c < PA; ++c) {
-      const T av = ab[g] * Lc[c];
-      accr = Mfma<T>::mma(av, br[g * PA + c], accr);
-      acci = Mfma<T>::mma(av, bi[g * PA + c], acci);
+      for (int i = 0; i < 8; ++i) {
+        const int v = 8 * st + i;
+        const float x = v < NK ? ab[v < NK ? v / PA : 0] * Lc[v < NK ? v % PA : 0] : 0.f;
+        const __bf16 h = (__bf16)x;
+        ah[i] = h;
+        al[i] = (__bf16)(x - (float)h);
+      }
+      accr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, sb.rh[st], accr, 0, 0, 0);
+      acci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, sb.ih[st], acci, 0, 0, 0);
+      accr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, sb.rl[st], accr, 0, 0, 0);
+      acci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, sb.il[st], acci, 0, 0, 0);
+      accr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, sb.rh[st], accr, 0, 0, 0);
+      acci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, sb.ih[st], acci, 0, 0, 0);
     }
+  } else {
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+      for (int c = 0; c < PA; ++c) {
+        const T av = ab[g] * Lc[c];
+        accr = Mfma<T>::mma(av, br[g * PA + c], accr);
+        acci = Mfma<T>::mma(av, bi[g * PA + c], acci);
+      }
+  }
   if (colok) {
     CT y0[4];
 #pragma unroll
@@ -1505,7 +1562,7 @@ __device__ __forceinline__ void small_tile(const T* s_L, const T* s_u, const Che
 // contiguous ranges, one per wave.  Within an octant every (box, node) is
 // written by exactly one item (M-tiles of different child cones hold
 // different nodes), so the block-wide accumulators need no atomics.
-template <int PS, int PA, typename T, int MAXR, int NWV>
+template <int PS, int PA, typename T, int MAXR, int NWV, bool SPLIT>
 __global__ void __launch_bounds__(64 * NWV, sizeof(T) == 4 ? 3 : 2)
 prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc,
                   typename C2<T>::type* __restrict__ Vp) {
@@ -1721,9 +1778,12 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
       }
       T br[SP::NK], bi[SP::NK];
       small_load_b<PS, PA, T, MAXR>(Vc + ((int64_t)(cs >= 0 ? cs : 0) * nrhs + r) * P, kq, br, bi);
+      SplitB<SP::NK> sb;
+      if constexpr (SPLIT) split_b<SP::NK>((const float*)br, (const float*)bi, sb);
       do {
-        small_tile<PS, PA, T, MAXR, LREG>(s_L, s_u, A.cheb, wak, wbk, s_ratp, s_rows, s_y, rb,
-                                          min(16, rend - rb), yb, colok, lane, br, bi);
+        small_tile<PS, PA, T, MAXR, LREG, SPLIT>(s_L, s_u, A.cheb, wak, wbk, s_ratp, s_rows, s_y,
+                                                 rb, min(16, rend - rb), yb, colok, lane, br,
+                                                 bi, sb);
         ++item;
         rb += 16;
       } while (item < i1 && rb < rend);
@@ -2036,7 +2096,7 @@ static void launch_grouped(const ApplyArgs& A, int l, const typename C2<T>::type
   }
 }
 
-template <int PS, int PA, typename T, int MAXR>
+template <int PS, int PA, typename T, int MAXR, bool SPLIT>
 static hipError_t apply_impl(const ApplyArgs& A, const void* dens_user,
                              void* out_user, hipStream_t st, Profiler* prof) {
   typedef typename C2<T>::type CT;
@@ -2069,11 +2129,11 @@ static hipError_t apply_impl(const ApplyArgs& A, const void* dens_user,
             IFGF_TIMED(6, (launch_grouped<PS, PA, T, MAXR>(A, l, Vcur, Vnext, Qh.nchunks, st)));
             done = true;
           } else if (Qh.prop_grouped == kPropSmall) {
-            IFGF_TIMED(7, (prop_small_kernel<PS, PA, T, MAXR, 1>
+            IFGF_TIMED(7, (prop_small_kernel<PS, PA, T, MAXR, 1, SPLIT>
                            <<<(unsigned)Qh.nschunks, 64, 0, st>>>(A, l, Vcur, Vnext)));
             done = true;
           } else if (Qh.prop_grouped == kPropMedium) {
-            IFGF_TIMED(7, (prop_small_kernel<PS, PA, T, MAXR, kMediumWaves>
+            IFGF_TIMED(7, (prop_small_kernel<PS, PA, T, MAXR, kMediumWaves, SPLIT>
                            <<<(unsigned)Qh.nmchunks, 64 * kMediumWaves, 0, st>>>(A, l, Vcur,
                                                                                  Vnext)));
             done = true;
@@ -2093,7 +2153,7 @@ static hipError_t apply_impl(const ApplyArgs& A, const void* dens_user,
   return hipGetLastError();
 }
 
-template <int PS, int PA, typename T, int MAXR>
+template <int PS, int PA, typename T, int MAXR, bool SPLIT>
 static hipError_t prop_level_impl(const ApplyArgs& A, int l, int kind,
                                   hipStream_t st) {
   typedef typename C2<T>::type CT;
@@ -2108,11 +2168,11 @@ static hipError_t prop_level_impl(const ApplyArgs& A, int l, int kind,
       return hipGetLastError();
     }
     if (kind == kPropSmall && Qh.nschunks > 0) {
-      prop_small_kernel<PS, PA, T, MAXR, 1><<<(unsigned)Qh.nschunks, 64, 0, st>>>(A, l, Vc, Vp);
+      prop_small_kernel<PS, PA, T, MAXR, 1, SPLIT><<<(unsigned)Qh.nschunks, 64, 0, st>>>(A, l, Vc, Vp);
       return hipGetLastError();
     }
     if (kind == kPropMedium && Qh.nmchunks > 0) {
-      prop_small_kernel<PS, PA, T, MAXR, kMediumWaves>
+      prop_small_kernel<PS, PA, T, MAXR, kMediumWaves, SPLIT>
           <<<(unsigned)Qh.nmchunks, 64 * kMediumWaves, 0, st>>>(A, l, Vc, Vp);
       return hipGetLastError();
     }
@@ -2126,10 +2186,13 @@ hipError_t launch_prop_level(const ApplyArgs& A, int l, int ps, int pa,
 #define IFGF_PL(PS_, PA_)                                                      \
   if (ps == PS_ && pa == PA_) {                                                \
     if (precision == 0)                                                        \
-      return A.nrhs <= 1 ? prop_level_impl<PS_, PA_, double, 1>(A, l, kind, st) \
-                         : prop_level_impl<PS_, PA_, double, kMaxRhs>(A, l, kind, st); \
-    return A.nrhs <= 1 ? prop_level_impl<PS_, PA_, float, 1>(A, l, kind, st) \
-                       : prop_level_impl<PS_, PA_, float, kMaxRhs>(A, l, kind, st); \
+      return A.nrhs <= 1 ? prop_level_impl<PS_, PA_, double, 1, false>(A, l, kind, st) \
+                         : prop_level_impl<PS_, PA_, double, kMaxRhs, false>(A, l, kind, st); \
+    if (precision == 2)                                                        \
+      return A.nrhs <= 1 ? prop_level_impl<PS_, PA_, float, 1, true>(A, l, kind, st) \
+                         : prop_level_impl<PS_, PA_, float, kMaxRhs, true>(A, l, kind, st); \
+    return A.nrhs <= 1 ? prop_level_impl<PS_, PA_, float, 1, false>(A, l, kind, st) \
+                       : prop_level_impl<PS_, PA_, float, kMaxRhs, false>(A, l, kind, st); \
   }
   IFGF_PL(3, 5)
   IFGF_PL(2, 3)
@@ -2145,11 +2208,15 @@ hipError_t launch_apply(const ApplyArgs& A, int ps, int pa, int precision,
   if (ps == PS_ && pa == PA_) {                                               \
     if (precision == 0)                                                       \
       return A.nrhs <= 1                                                      \
-                 ? apply_impl<PS_, PA_, double, 1>(A, dens_user, out_user, st, prof) \
-                 : apply_impl<PS_, PA_, double, kMaxRhs>(A, dens_user, out_user, st, prof); \
+                 ? apply_impl<PS_, PA_, double, 1, false>(A, dens_user, out_user, st, prof) \
+                 : apply_impl<PS_, PA_, double, kMaxRhs, false>(A, dens_user, out_user, st, prof); \
+    if (precision == 2)                                                       \
+      return A.nrhs <= 1                                                      \
+                 ? apply_impl<PS_, PA_, float, 1, true>(A, dens_user, out_user, st, prof) \
+                 : apply_impl<PS_, PA_, float, kMaxRhs, true>(A, dens_user, out_user, st, prof); \
     return A.nrhs <= 1                                                        \
-               ? apply_impl<PS_, PA_, float, 1>(A, dens_user, out_user, st, prof) \
-               : apply_impl<PS_, PA_, float, kMaxRhs>(A, dens_user, out_user, st, prof); \
+               ? apply_impl<PS_, PA_, float, 1, false>(A, dens_user, out_user, st, prof) \
+               : apply_impl<PS_, PA_, float, kMaxRhs, false>(A, dens_user, out_user, st, prof); \
   }
   IFGF_APPLY(3, 5)
   IFGF_APPLY(2, 3)

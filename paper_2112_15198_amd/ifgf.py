@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libifgf.so")
 
 IFGF_MAX_LEVELS = 24
-FP64, FP32_MIXED = 0, 1
+FP64, FP32_MIXED, FP32_BF16X3 = 0, 1, 2
 
 STATUS = {0: "IFGF_OK", 1: "IFGF_EINVAL", 2: "IFGF_ENOMEM", 3: "IFGF_EDUPLICATE",
           4: "IFGF_EHIP", 5: "IFGF_EUNSUPPORTED", 6: "IFGF_ELOOKUP"}
@@ -115,7 +115,8 @@ def _opts(precision, n_rhs, leaf_grid, levels, stages, host_only, device,
     o = Opts()
     _check(load_library().ifgf_default_opts(ctypes.byref(o)))
     o.precision = {"fp64": FP64, "fp32": FP32_MIXED, "mixed": FP32_MIXED,
-                   FP64: FP64, FP32_MIXED: FP32_MIXED}[precision]
+                   "bf16x3": FP32_BF16X3, FP64: FP64, FP32_MIXED: FP32_MIXED,
+                   FP32_BF16X3: FP32_BF16X3}[precision]
     o.n_rhs = int(n_rhs)
     o.leaf_grid[0], o.leaf_grid[1], o.leaf_grid[2] = (int(v) for v in leaf_grid)
     o.levels = int(levels)

@@ -147,7 +147,7 @@ def test_other_orders_match_oracle(ps, pa):
 
 
 @pytest.mark.parametrize("prop", ["auto", "grouped", "small", "medium", "node"])
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
 def test_multi_rhs_equals_single_rhs(precision, prop):
     n = 6000
     p = W.spheroid(n)
@@ -155,7 +155,7 @@ def test_multi_rhs_equals_single_rhs(precision, prop):
     a = W.densities(n, 4, 35)
     say("multi-rhs", precision, prop)
     g4, _ = run_gpu(p, a, k, precision=precision, prop_kernel=prop)
-    tol = 1e-13 if precision == "fp64" else 1e-6
+    tol = 1e-13 if precision == "fp64" else 1e-6 if precision == "fp32" else 1e-5
     for r in range(4):
         g1, _ = run_gpu(p, a[r:r + 1], k, precision=precision, prop_kernel=prop)
         assert relerr(g4[r], g1[0]) <= tol
@@ -252,11 +252,13 @@ def test_relevant_cones_match_oracle_exactly(geom):
                                          ("grouped", "hash"), ("node", "hash"),
                                          ("small", "auto"), ("small", "hash"),
                                          ("medium", "auto")])
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 2e-5)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 2e-5), ("bf16x3", 2e-5)])
 def test_kernel_variants_match_oracle(prop, lookup, precision, tol):
     """Per-node, matrix-core block and wave-task (one and four waves)
     propagation, dense and hashed cone look-up: all agree with the oracle
-    IFGF (FP64: 1e-10; FP32-mixed: 2e-5, its rounding)."""
+    IFGF (FP64: 1e-10; FP32-mixed: 2e-5, its rounding, measured 3e-7;
+    FP32 with the three-term BF16 product: 2e-5, about 2^-16 per product
+    through the levels, measured 3e-6)."""
     n = 7000
     p = W.fibonacci_sphere(n)
     k = W.kappa_sphere_10ppw(n)
@@ -286,7 +288,7 @@ def test_wave_task_kernels_match_per_node_at_scale(n_rhs):
 
 
 @pytest.mark.parametrize("prop", ["grouped", "small", "medium"])
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-6), ("bf16x3", 1e-6)])
 def test_graph_replays_match_eager(precision, tol, prop):
     """The HIP-graph apply, replayed several times with eager work and
     synchronisations in between, matches the eager apply every time."""

@@ -22,7 +22,7 @@ def say(*a):
 def graph_apply(pl, dens, precision, graph=True):
     """Two applies into one output (graph replays when graph=True)."""
     import torch
-    dt = torch.complex64 if precision == "fp32" else torch.complex128
+    dt = torch.complex128 if precision == "fp64" else torch.complex64
     a = torch.from_numpy(np.ascontiguousarray(dens)).to(dt).cuda()
     out = torch.empty_like(a)
     for _ in range(2):
@@ -36,24 +36,28 @@ def relerr(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-@pytest.mark.parametrize("name", ["oblate_1m", "sphere_5m"])
-def test_full_size_fp32_vs_direct_sum(name):
-    """oblate_1m (N = 1,048,576, kappa 64 pi, 4 RHS) and sphere_5m
-    (N = 5,144,576, kappa 128 pi): every RHS within 1e-4 of the FP64 direct
-    sum on 512 of the workload's 4,096 sampled targets."""
+@pytest.mark.parametrize("name,precision", [("oblate_1m", "fp32"), ("sphere_5m", "fp32"),
+                                            ("sphere_321k", "bf16x3"),
+                                            ("oblate_1m", "bf16x3")])
+def test_full_size_vs_direct_sum(name, precision):
+    """oblate_1m (N = 1,048,576, kappa 64 pi, 4 RHS), sphere_5m
+    (N = 5,144,576, kappa 128 pi) and sphere_321k (N = 321,536, kappa 32 pi),
+    FP32-mixed and with the three-term BF16 propagation product: every RHS
+    within 1e-4 of the FP64 direct sum on 512 of the workload's 4,096
+    sampled targets."""
     import paper_2112_15198_amd as ifgf
     w = W.make(name)
     n_rhs = w.dens.shape[0]
     tg = w.targets[::8]
-    say("full size", name, "N", w.points.shape[0], "rhs", n_rhs)
-    pl = ifgf.plan(w.points, w.kappa, precision="fp32", n_rhs=n_rhs,
+    say("full size", name, precision, "N", w.points.shape[0], "rhs", n_rhs)
+    pl = ifgf.plan(w.points, w.kappa, precision=precision, n_rhs=n_rhs,
                    leaf_grid=(2, 4, 8), autotune=True)
-    out = graph_apply(pl, w.dens, "fp32")
+    out = graph_apply(pl, w.dens, precision)
     pl.close()
     for r in range(n_rhs):
         ref = oracle.direct_sum(w.points, w.dens[r], w.kappa, tg)
         e = relerr(out[r][tg], ref)
-        say(name, "rhs", r, "rel-err", f"{e:.3e}")
+        say(name, precision, "rhs", r, "rel-err", f"{e:.3e}")
         assert e <= 1e-4, (name, r, e)
 
 

@@ -85,6 +85,17 @@ def test_error_codes():
     assert _status(lambda: ifgf.plan(p, 3.0, n_rhs=9)) == 5
     assert _status(lambda: ifgf.plan(p, 3.0, leaf_grid=(0, 4, 8))) == 1
     assert _status(lambda: ifgf.plan(p, 3.0, levels=2, host_only=True)) == 1
+    # Precision: the three modes plan (host only); another value is EINVAL.
+    for prec in ("fp64", "fp32", "bf16x3"):
+        ifgf.plan(p, 3.0, precision=prec, host_only=True).close()
+    import ctypes
+    o = lib._opts("fp32", 1, (2, 4, 8), 0, 3, True, None)
+    o.precision = 3
+    h = ctypes.c_void_p()
+    pts = np.ascontiguousarray(p)
+    rc = lib.load_library().ifgf_plan_ex(ctypes.byref(h), pts.ctypes.data_as(ctypes.c_void_p),
+                                         pts.shape[0], 3.0, 3, 5, 0.25, ctypes.byref(o))
+    assert rc == 1
 
 
 def test_status_strings():
