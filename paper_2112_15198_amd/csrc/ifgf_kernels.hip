@@ -1335,15 +1335,16 @@ prop_big_kernel(ApplyArgs A, int l, const float2* __restrict__ Vc, float2* __res
 
 // Matrix-core propagation for levels where few to some hundred boxes share
 // a parent cone index.  A block of NWV waves takes a chunk of up to NWV * WB
-// parent boxes sharing (instance, gamma'); wave w owns the boxes
-// w WB .. w WB + WB - 1 and accumulates their cones in its own LDS slice.
-// Octant by octant the block computes the node geometry (child cone, local
-// coordinates, ratio) of the nodes and groups them by child cone, once for
-// all its waves; every wave then multiplies
+// parent boxes sharing (instance, gamma') and accumulates their cones in
+// LDS.  Octant by octant the block computes the node geometry (child cone,
+// local coordinates, ratio) of the nodes, groups them by child cone and
+// compacts the children of its boxes in the octant; the waves then share
+// the products
 //     C[p][(box, rhs)] = sum_q W[p][q] X[q][(box, rhs)]
-// on 16x16x4 MFMA tiles (one N-tile: its boxes with a child in the
-// octant), W[p][q] = L_a(u_s) L_b(u_theta) L_c(u_phi) formed per tile, and
-// adds ratio(p) * C to its slice.  The factors L_a, L_b, L_c of a row come
+// on 16x16x4 MFMA tiles (an N-tile: 16 (child, rhs) columns; an M-tile: up
+// to 16 nodes of one child cone), W[p][q] = L_a(u_s) L_b(u_theta) L_c(u_phi)
+// formed per tile, adding ratio(p) * C to the accumulators.  The factors
+// L_a, L_b, L_c of a row come
 // from LDS (several waves: formed once per octant) or are evaluated in
 // registers per tile (one wave: the LDS they would take keeps a third wave
 // per SIMD resident).
