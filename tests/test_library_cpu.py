@@ -102,3 +102,24 @@ def test_status_strings():
     L = ifgf.load_library()
     for s in range(7):
         assert L.ifgf_status_string(s)
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    """Without libifgf.so the binding raises; there is no CPU fallback."""
+    monkeypatch.setattr(lib, "LIB_PATH", str(tmp_path / "libifgf.so"))
+    monkeypatch.setattr(lib, "_lib", None)
+    with pytest.raises(RuntimeError, match="is missing"):
+        lib.load_library()
+    with pytest.raises(RuntimeError, match="is missing"):
+        ifgf.plan(W.fibonacci_sphere(100), 3.0, host_only=True)
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU; --gpus 2 exits with a message before any
+    GPU work."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stdout
