@@ -49,7 +49,7 @@ struct StepDev {
   // Propagation into this step, grouped: the relevant cones sorted by
   // (instance, gamma, box) and cut into chunks of boxes sharing one gamma,
   // whose node geometry is computed once per chunk.
-  int prop_grouped;           // kernel: kPropNode, kPropGrouped or kPropSmall
+  int prop_grouped;           // kernel: kPropNode, kPropGrouped, kPropSmall or kPropMedium
   int64_t nchunks;
   const int* gslot;           // slots in (instance, gamma, box) order
   const int64_t* chunk_start; // first index into gslot of each chunk
@@ -143,7 +143,8 @@ hipError_t sort_keys(unsigned long long* keys, unsigned long long* tmp,
                      int64_t n, int end_bit, void* scratch,
                      size_t* scratch_bytes, hipStream_t st);
 // One Propagation launch (step l -> l + 1) with kernel `kind` (kPropNode,
-// kPropGrouped, kPropSmall), for timing at plan time.
+// kPropGrouped, kPropSmall, kPropMedium), for timing at plan time;
+// precision 0 FP64, 1 FP32-mixed, 2 FP32 with the three-term BF16 product.
 hipError_t launch_prop_level(const ApplyArgs& A, int l, int ps, int pa,
                              int precision, int kind, hipStream_t st);
 hipError_t launch_apply(const ApplyArgs& A, int ps, int pa, int precision,
