@@ -382,6 +382,7 @@ interp_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V,
   T accr[MAXR], acci[MAXR];
 #pragma unroll
   for (int r = 0; r < MAXR; ++r) accr[r] = acci[r] = 0;
+  bool miss = false;  // a cone look-up missed (reported once, after the loop)
   for (int64_t j = S.cous_begin[b]; j < S.cous_begin[b + 1]; ++j) {
     int k = S.cous[j];
     double y0, y1, y2;
@@ -400,7 +401,7 @@ interp_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V,
                              ((unsigned long long)is * S.nt + it) * S.np + ip;
     int slot = cone_lookup(S, key);
     if (slot < 0) {
-      atomicOr(A.err, 1);
+      miss = true;
       continue;
     }
     T Ls[PS], Lt[PA], Lp[PA];
@@ -420,6 +421,7 @@ interp_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V,
       acci[r2] += vr * gs + vi * gc;
     }
   }
+  if (miss) atomicOr(A.err, 1);
   for (int r2 = 0; r2 < A.nrhs && r2 < MAXR; ++r2) {
     typename C2<T>::type v = out[i * A.nrhs + r2];
     v.x += accr[r2];
@@ -467,6 +469,7 @@ prop_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc,
   T accr[MAXR], acci[MAXR];
 #pragma unroll
   for (int r = 0; r < MAXR; ++r) accr[r] = acci[r] = 0;
+  bool miss = false;  // a cone look-up missed (reported once, after the loop)
   for (int o = 0; o < 8; ++o) {
     int k = Q.child[8 * j + o];
     if (k < 0) continue;
@@ -486,7 +489,7 @@ prop_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc,
                               ((unsigned long long)cs * S.nt + ct) * S.np + cp;
     int cslot = cone_lookup(S, ckey);
     if (cslot < 0) {
-      atomicOr(A.err, 1);
+      miss = true;
       continue;
     }
     T Ls[PS], Lt[PA], Lp[PA];
@@ -507,6 +510,7 @@ prop_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc,
       acci[r2] += vr * gs + vi * gc;
     }
   }
+  if (miss) atomicOr(A.err, 1);
   for (int r2 = 0; r2 < A.nrhs && r2 < MAXR; ++r2) {
     typename C2<T>::type v;
     v.x = accr[r2];
@@ -1642,6 +1646,7 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
   const int col = lane & 15, kq = lane >> 4;
   const T wak = kq < PS ? (T)A.cheb.ws[kq] : (T)0;
   const T wbk = kq < SP::PB ? (T)A.cheb.wa[kq] : (T)0;
+  bool miss = false;  // a cone look-up missed (reported once, at the end)
 #pragma unroll 1
   for (int o = 0; o < 8; ++o) {
     const int no = s_no[o];
@@ -1743,7 +1748,7 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
       for (int e = tid; e < no * nac; e += 64 * NWV) {
         const int k = e / no, n = e - k * no;
         const int cs = cone_lookup(S, (unsigned long long)s_ch[o][n] * S.ngrid + s_dist[k]);
-        if (cs < 0) atomicOr(A.err, 1);
+        miss |= cs < 0;
         s_cs[n * NAMAX + k] = cs;
       }
     }
@@ -1775,7 +1780,7 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
         cs = s_cs[n0 * NAMAX + k];
       } else {
         cs = cone_lookup(S, (unsigned long long)s_ch[o][n0] * S.ngrid + s_dist[k]);
-        if (cs < 0) atomicOr(A.err, 1);
+        miss |= cs < 0;
       }
       T br[SP::NK], bi[SP::NK];
       small_load_b<PS, PA, T, MAXR>(Vc + ((int64_t)(cs >= 0 ? cs : 0) * nrhs + r) * P, kq, br, bi);
@@ -1799,6 +1804,7 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
     }
     __syncthreads();
   }
+  if (miss) atomicOr(A.err, 1);
   // Write the parent cones of the chunk's boxes.
   for (int i = tid; i < nb * nrhs * P; i += 64 * NWV) {
     const int n = i / (nrhs * P);
