@@ -236,7 +236,13 @@ def plan(points, kappa, p_s=3, p_ang=5, leaf_size=0.25, precision="fp64",
          n_rhs=1, leaf_grid=(2, 4, 8), levels=0, stages=3, host_only=False,
          device=None, cone_margin=None, prop_kernel="auto", lookup="auto",
          autotune=False):
-    """Plan one instance; points is an (N, 3) float64 array (host)."""
+    """Plan one instance; points is an (N, 3) float64 array (host).
+
+    precision: "fp64" (IFGF_FP64, complex128 densities), "fp32"
+    (IFGF_FP32_MIXED, complex64) or "bf16x3" (IFGF_FP32_BF16X3, complex64:
+    FP32-mixed with the wave-task propagation product in three-term BF16
+    form).  prop_kernel: "auto", "node", "grouped", "small" (one-wave) or
+    "medium" (four-wave); autotune=True times the four per level instead."""
     pts = np.ascontiguousarray(np.asarray(points, dtype=np.float64))
     if pts.ndim != 2 or pts.shape[1] != 3:
         raise ValueError("points must have shape (N, 3)")
