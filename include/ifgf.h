@@ -14,8 +14,10 @@
  *   - Every function returns an ifgf_status; on error nothing is written to
  *     the caller's output and ifgf_status_string() describes the failure
  *     (for IFGF_EHIP it includes the HIP error of the failing call).
- *   - Points are FP64, N x 3 row-major, in HOST memory.  Densities and
- *     outputs are DEVICE pointers on the plan's GPU.
+ *   - Points are FP64, N x 3 row-major, in host or device memory (device
+ *     points are copied to the host, where the octree is built; a
+ *     host_only plan needs host points).  Densities and outputs are DEVICE
+ *     pointers on the plan's GPU.
  *   - Complex numbers are interleaved (re, im): complex128 (two doubles) in
  *     IFGF_FP64 mode, complex64 (two floats) in IFGF_FP32_MIXED and
  *     IFGF_FP32_BF16X3 modes.
@@ -35,8 +37,10 @@ typedef struct ifgf_plan_s* ifgf_plan_t; /* opaque, owned by the library */
 
 typedef enum {
   IFGF_OK = 0,
-  IFGF_EINVAL = 1,      /* n < 2, kappa <= 0, p < 1, NaN/Inf coordinates,
-                           bad options, null pointers */
+  IFGF_EINVAL = 1,      /* n < 2, kappa < 0 or non-finite, kappa = 0
+                           without a wavelength-free level rule (levels or
+                           leaf_abs), p < 1, NaN/Inf coordinates, bad
+                           options, null pointers */
   IFGF_ENOMEM = 2,      /* host or device allocation failed */
   IFGF_EDUPLICATE = 3,  /* two identical points: eq. (field1) is singular */
   IFGF_EHIP = 4,        /* a HIP runtime call failed */
@@ -64,10 +68,14 @@ typedef struct ifgf_opts {
                        beyond the paper). */
   int n_rhs;        /* number of right-hand sides per apply, >= 1 */
   int leaf_grid[3]; /* cone-segment grid (n_s, n_theta, n_phi) at the leaf
-                       level D; each level up doubles every dimension.
+                       level D; see grid_rule for the other levels.
                        {0,0,0} selects the default {2,4,8}. */
-  int levels;       /* number of octree levels D; 0 selects
-                       D = max(3, 1 + round(log2(H_1 / (leaf_size lambda)))) */
+  int levels;       /* number of octree levels D of every instance; 0
+                       selects D per instance by the level rule:
+                       D = max(3, 1 + round(log2(H_1 / w))) with w = leaf_abs
+                       if leaf_abs > 0, else w = leaf_size * lambda
+                       (lambda = 2 pi / kappa); then, if leaf_max > 0, D
+                       grows by one while H_1 / 2^(D-1) > leaf_max * lambda */
   int stages;       /* bit 0: near field (level-D neighbours, direct sum);
                        bit 1: far field (IFGF levels D..3).  0 means both. */
   int host_only;    /* 1: build the host octree only (no GPU used); only
@@ -92,6 +100,30 @@ typedef struct ifgf_opts {
                        that look-ups along other rounding paths never miss;
                        default 1e-9; 0 gives exactly the point-based
                        relevant cones of eq. (relevantconesegments) */
+  double leaf_max;  /* per-instance accuracy control: cap on the leaf box
+                       side in wavelengths (0: no cap).  The rounding of the
+                       level rule puts leaves between 0.71 and 1.41 times
+                       leaf_size; the method's error grows with the leaf
+                       side (Section "Numerical error estimation"), and a
+                       cap adds a level to an instance whose leaves would be
+                       wider.  Ignored for kappa = 0. */
+  double leaf_abs;  /* leaf box side in the points' length unit (0: use
+                       leaf_size wavelengths).  The level rule for the
+                       Laplace kernel (kappa = 0), which has no wavelength. */
+  int grid_rule;    /* cone grid of the levels above the leaf: 0 doubles
+                       every dimension per level up when kappa > 0 (the
+                       phase varies over a box of side H_d at the scale
+                       kappa H_d) and keeps the leaf grid at every level
+                       when kappa = 0 (the analytic factor is then
+                       scale-free in (s, theta, phi)); 1 always doubles;
+                       2 always keeps the leaf grid.  One batched plan
+                       cannot mix kappa = 0 and kappa > 0 under rule 0. */
+  const char* tune_cache; /* path of the autotuner's cache file (NULL or
+                       "": none).  With autotune = 1, a plan whose shape,
+                       precision, RHS count and kernel build match a line
+                       of the file takes the kernels recorded there instead
+                       of timing them, and a plan that times them appends a
+                       line. */
 } ifgf_opts;
 
 /* Size information about a plan (ifgf_plan_info). */
@@ -122,6 +154,8 @@ typedef struct ifgf_info {
   int64_t near_pairs;     /* (target, source) near-field pairs, self included */
   int64_t device_bytes;   /* device memory held by the plan */
   double plan_seconds;    /* wall time of plan construction */
+  int tune_cache_hit;     /* 1 when the kernels came from the tuning cache */
+  int grid_doubling;      /* 1 when the cone grid doubles per level up */
 } ifgf_info;
 
 /* Fill *opts with the defaults: FP64, 1 RHS, leaf grid {2,4,8}, automatic
@@ -130,7 +164,9 @@ ifgf_status ifgf_default_opts(ifgf_opts* opts);
 
 /* Plan one instance (Section 2 of the paper: octree, relevant boxes,
  * neighbour and cousin lists, relevant cone segments; Morton ordering of
- * Section 3.2).  points: N x 3 FP64 host array, copied.  kappa > 0.
+ * Section 3.2).  points: N x 3 FP64 array (host or device), copied.
+ * kappa > 0 (kappa = 0, the Laplace kernel, needs opts.leaf_abs or
+ * opts.levels through ifgf_plan_ex).
  * p_s, p_ang: Chebyshev points per cone in the radial and in each angular
  * variable (P = p_s * p_ang^2 interpolation points per cone); compiled
  * kernels exist for (3,5), (2,3) and (5,7).  leaf_size: leaf box side in
@@ -144,7 +180,8 @@ ifgf_status ifgf_plan_ex(ifgf_plan_t* plan, const double* points, int64_t n,
                          const ifgf_opts* opts);
 
 /* Plan n_inst independent instances evaluated together by every apply
- * (each kernel launch processes all instances).  Instance i owns points
+ * (each kernel launch processes all instances): the batched form of the
+ * operator of eq. (field1), one independent sum per instance.  Instance i owns points
  * [offsets[i], offsets[i+1]) of the host array `points` (offsets has n_inst+1
  * entries, offsets[0] = 0), wavenumber kappas[i].  Densities and outputs of
  * a batched apply are [n_rhs][N_total], N_total = offsets[n_inst], in that
@@ -158,7 +195,9 @@ ifgf_status ifgf_plan_batched(ifgf_plan_t* plan, int n_inst,
  * densities, out: device pointers, [n_rhs][N] interleaved complex of the
  * plan's precision (complex128 for IFGF_FP64, complex64 for
  * IFGF_FP32_MIXED and IFGF_FP32_BF16X3); out is overwritten.  Asynchronous with respect to the
- * host; one apply at a time per plan (not re-entrant). */
+ * host; one apply at a time per plan (not re-entrant).  A cone look-up that
+ * misses (an internal consistency error) is skipped and only flagged: call
+ * ifgf_check after the apply before trusting its result. */
 ifgf_status ifgf_apply(ifgf_plan_t plan, const void* densities, void* out);
 
 /* As ifgf_apply, through a HIP graph: the first call for a (densities,

@@ -31,11 +31,11 @@ def _load():
         c_i64, c_dbl, c_int = ctypes.c_int64, ctypes.c_double, ctypes.c_int
         P = ctypes.c_void_p
         lib.oracle_direct_sum.argtypes = [P, c_i64, P, c_dbl, P, c_i64, P]
-        lib.oracle_ifgf.argtypes = [P, c_i64, P, c_dbl, c_dbl, P, P, P]
-        lib.oracle_partition_counts.argtypes = [P, c_i64, c_dbl, c_dbl, c_int, P]
+        lib.oracle_ifgf.argtypes = [P, c_i64, P, c_dbl, c_dbl, P, P, P, P]
+        lib.oracle_partition_counts.argtypes = [P, c_i64, c_dbl, c_dbl, P, P, P]
         lib.oracle_interp_nodes.argtypes = [c_int, c_int, P, P]
         lib.oracle_interp_eval.argtypes = [c_int, c_int, P, P, c_i64, P]
-        lib.oracle_cone_keys.argtypes = [P, c_i64, c_dbl, c_dbl, P, c_int, P, c_i64]
+        lib.oracle_cone_keys.argtypes = [P, c_i64, c_dbl, c_dbl, P, P, c_int, P, c_i64]
         lib.oracle_cone_keys.restype = c_i64
         for f in (lib.oracle_direct_sum, lib.oracle_ifgf,
                   lib.oracle_partition_counts, lib.oracle_interp_nodes,
@@ -76,20 +76,41 @@ def direct_sum(points, dens, kappa, targets=None):
     return out.view(np.complex128)
 
 
+GRID_RULES = {"auto": 0, "double": 1, "constant": 2}
+
+
+def _options(p_s, p_ang, leaf_grid, levels, exact, stages, grid_rule, leaf_max,
+             leaf_abs):
+    """Flat option arrays of the C interface.
+
+    Levels: ``levels`` if > 0, else D = max(3, 1 + round(log2(H_1 / s)))
+    with s = leaf_abs (length units) if > 0, else leaf_size wavelengths;
+    then, if leaf_max > 0 (wavelengths), one more level while the leaf side
+    exceeds leaf_max wavelengths.  grid_rule: "auto" (the leaf cone grid
+    doubles per level up for kappa > 0, constant for kappa = 0), "double"
+    or "constant"."""
+    opts = np.array([p_s, p_ang, leaf_grid[0], leaf_grid[1], leaf_grid[2],
+                     levels, 1 if exact else 0, stages,
+                     GRID_RULES[grid_rule]], dtype=np.int32)
+    dopts = np.array([leaf_max, leaf_abs], dtype=np.float64)
+    return opts, dopts
+
+
 def ifgf(points, dens, kappa, p_s=3, p_ang=5, leaf_size=0.25,
          leaf_grid=(1, 2, 4), levels=0, exact=False, near=True, far=True,
-         return_info=False):
+         return_info=False, grid_rule="auto", leaf_max=0.0, leaf_abs=0.0):
     """Plain FP64 IFGF of eq. (field1) at every point (user order)."""
     p = _pts(points)
     n = p.shape[0]
     a = _dens(dens, n)
-    opts = np.array([p_s, p_ang, leaf_grid[0], leaf_grid[1], leaf_grid[2],
-                     levels, 1 if exact else 0,
-                     (1 if near else 0) | (2 if far else 0)], dtype=np.int32)
+    opts, dopts = _options(p_s, p_ang, leaf_grid, levels, exact,
+                           (1 if near else 0) | (2 if far else 0), grid_rule,
+                           leaf_max, leaf_abs)
     out = np.zeros(2 * n, dtype=np.float64)
     info = np.zeros(2 + 2 * 32, dtype=np.float64)
     rc = _load().oracle_ifgf(_ptr(p), n, _ptr(a), float(kappa),
-                             float(leaf_size), _ptr(opts), _ptr(out), _ptr(info))
+                             float(leaf_size), _ptr(opts), _ptr(dopts), _ptr(out),
+                             _ptr(info))
     if rc != 0:
         raise RuntimeError(f"oracle_ifgf failed ({rc})")
     res = out.view(np.complex128)
@@ -101,13 +122,15 @@ def ifgf(points, dens, kappa, p_s=3, p_ang=5, leaf_size=0.25,
                  "cones": [int(info[2 * d + 1]) for d in range(1, D + 1)]}
 
 
-def partition_counts(points, kappa, leaf_size=0.25, levels=0):
+def partition_counts(points, kappa, leaf_size=0.25, levels=0, leaf_max=0.0,
+                     leaf_abs=0.0):
     """Per-target number of sources covered by near field plus cousins."""
     p = _pts(points)
     n = p.shape[0]
+    opts, dopts = _options(1, 1, (1, 2, 4), levels, False, 0, "auto", leaf_max, leaf_abs)
     out = np.zeros(n, dtype=np.int64)
-    rc = _load().oracle_partition_counts(_ptr(p), n, float(kappa),
-                                         float(leaf_size), int(levels), _ptr(out))
+    rc = _load().oracle_partition_counts(_ptr(p), n, float(kappa), float(leaf_size),
+                                         _ptr(opts), _ptr(dopts), _ptr(out))
     if rc != 0:
         raise RuntimeError(f"oracle_partition_counts failed ({rc})")
     return out
@@ -132,18 +155,19 @@ def interp_eval(p_s, p_ang, values, u):
 
 
 def cone_keys(points, kappa, level, p_s=3, p_ang=5, leaf_size=0.25,
-              leaf_grid=(1, 2, 4), levels=0):
+              leaf_grid=(1, 2, 4), levels=0, grid_rule="auto", leaf_max=0.0,
+              leaf_abs=0.0):
     """Sorted relevant-cone keys box * grid + gamma of octree level `level`."""
     p = _pts(points)
     n = p.shape[0]
-    opts = np.array([p_s, p_ang, leaf_grid[0], leaf_grid[1], leaf_grid[2],
-                     levels, 0, 0], dtype=np.int32)
+    opts, dopts = _options(p_s, p_ang, leaf_grid, levels, False, 0, grid_rule,
+                           leaf_max, leaf_abs)
     L = _load()
     cnt = L.oracle_cone_keys(_ptr(p), n, float(kappa), float(leaf_size),
-                             _ptr(opts), int(level), None, 0)
+                             _ptr(opts), _ptr(dopts), int(level), None, 0)
     if cnt < 0:
         raise RuntimeError("oracle_cone_keys failed")
     out = np.zeros(cnt, dtype=np.uint64)
     L.oracle_cone_keys(_ptr(p), n, float(kappa), float(leaf_size), _ptr(opts),
-                       int(level), _ptr(out), cnt)
+                       _ptr(dopts), int(level), _ptr(out), cnt)
     return out

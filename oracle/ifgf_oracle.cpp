@@ -19,13 +19,20 @@
 // them (all documented in the design notes of the repository):
 //   - root cube: bounding cube of the points, centred on the bounding box;
 //     box indices are clamped to [0, 2^(d-1) - 1] (points on the max face).
-//   - number of levels: D = max(3, 1 + round(log2(H_1 / (leaf_size * lambda)))).
+//   - number of levels: D = max(3, 1 + round(log2(H_1 / (leaf_size * lambda)))),
+//     or, with an absolute leaf side leaf_abs (the rule that needs no
+//     wavelength, used for the Laplace kernel kappa = 0),
+//     D = max(3, 1 + round(log2(H_1 / leaf_abs))); an optional cap leaf_max
+//     (in wavelengths) then adds levels until H_D <= leaf_max * lambda, which
+//     bounds the leaf side of instances whose size rounds badly.
 //   - cone coordinates about the box centre x_k: r = |x - x_k|,
 //     s = h/r with h = (sqrt 3 / 2) H_d, theta = atan2(sqrt(y1^2+y2^2), y3)
 //     in [0, pi], phi = atan2(y2, y1) mapped to [0, 2 pi); s in (0, eta] with
 //     eta = sqrt(3)/3.
 //   - cone grid: (n_s, n_theta, n_phi) at level D, doubled per dimension for
-//     each level up; cone index gamma = (i_s n_theta + i_theta) n_phi + i_phi
+//     each level up (kappa > 0); for kappa = 0 the analytic factor is
+//     scale-free in (s, theta, phi), so the same grid serves every level;
+//     cone index gamma = (i_s n_theta + i_theta) n_phi + i_phi
 //     ("radial first, then elevation, finally azimuth").
 //   - interpolation: tensor-product Chebyshev interpolation at first-kind
 //     Chebyshev nodes, P = P_s * P_ang * P_ang points per cone; interpolants are
@@ -133,6 +140,10 @@ struct Options {
   int levels;         // 0: automatic D
   int mode;           // 0: interpolated IFGF, 1: exact evaluations
   int stages;         // bit 0: near field, bit 1: far field (levels D..3)
+  int grid_rule = 0;  // 0: doubles per level up if kappa > 0, else constant;
+                      // 1: always doubles; 2: constant
+  double leaf_max = 0;  // cap on the leaf side in wavelengths (0: none)
+  double leaf_abs = 0;  // leaf side in length units (0: use leaf_size)
 };
 
 struct Oracle {
@@ -175,9 +186,17 @@ struct Oracle {
     for (int a = 0; a < 3; ++a) corner[a] = 0.5 * (lo[a] + hi[a]) - 0.5 * H1;
     if (o.levels > 0) {
       D = o.levels;
+    } else if (o.leaf_abs > 0) {
+      D = std::max(3, 1 + (int)std::llround(std::log2(H1 / o.leaf_abs)));
     } else {
       double lambda = 2.0 * PI / kappa;
       D = std::max(3, 1 + (int)std::llround(std::log2(H1 / (leaf_size * lambda))));
+    }
+    // Leaf-side cap: one more level while the leaf is wider than
+    // leaf_max wavelengths.
+    if (o.levels == 0 && o.leaf_max > 0 && kappa > 0) {
+      double lambda = 2.0 * PI / kappa;
+      while (D < 21 && std::ldexp(H1, -(D - 1)) > o.leaf_max * lambda) ++D;
     }
     lev.assign(D + 1, Level());
     double HD = std::ldexp(H1, -(D - 1));
@@ -348,7 +367,10 @@ struct Oracle {
     const double eta = std::sqrt(3.0) / 3.0;
     for (int d = 3; d <= D; ++d) {
       Level& L = lev[d];
-      int f = 1 << (D - d);
+      // Cone grid of level d: the leaf grid, doubled per dimension for each
+      // level up when it follows the wavelength.
+      const bool doubling = o.grid_rule == 1 || (o.grid_rule == 0 && kappa > 0);
+      int f = doubling ? 1 << (D - d) : 1;
       L.ns = o.ns * f;
       L.nt = o.nt * f;
       L.np = o.np * f;
@@ -631,19 +653,36 @@ struct Oracle {
   }
 };
 
-// opts: {p_s, p_ang, ns, nt, np, levels, mode, stages}
+// opts: {p_s, p_ang, ns, nt, np, levels, mode, stages, grid_rule}
+// dopts: {leaf_max, leaf_abs} (may be null: both 0)
 // info (optional, length >= 2 + 2*32): [D, H1, then per level d=1..D the
 // number of relevant boxes and relevant cones].
+// Options of the oracle from the flat arrays of the C interface; false when
+// they do not define a level rule (kappa = 0 needs levels or leaf_abs).
+static bool read_options(Options& o, const int* opts, const double* dopts,
+                         double kappa, double leaf_size) {
+  o = Options{opts[0], opts[1], opts[2], opts[3], opts[4], opts[5], opts[6], opts[7]};
+  o.grid_rule = opts[8];
+  if (dopts) {
+    o.leaf_max = dopts[0];
+    o.leaf_abs = dopts[1];
+  }
+  if (!(kappa >= 0) || !std::isfinite(kappa)) return false;
+  if (o.grid_rule < 0 || o.grid_rule > 2 || !(o.leaf_max >= 0) || !(o.leaf_abs >= 0)) return false;
+  if (o.levels == 0 && o.leaf_abs == 0 && !(kappa > 0 && leaf_size > 0)) return false;
+  return true;
+}
+
 extern "C" int oracle_ifgf(const double* pts, int64_t n, const double* dens,
                            double kappa, double leaf_size, const int* opts,
-                           double* out, double* info) {
-  if (n < 2 || !(kappa > 0) || !(leaf_size > 0)) return 1;
+                           const double* dopts, double* out, double* info) {
+  if (n < 2) return 1;
   Oracle O;
   O.n = n;
   O.x_user = pts;
   O.a_user = dens;
   O.kappa = kappa;
-  O.o = Options{opts[0], opts[1], opts[2], opts[3], opts[4], opts[5], opts[6], opts[7]};
+  if (!read_options(O.o, opts, dopts, kappa, leaf_size)) return 1;
   if (O.o.p_s < 1 || O.o.p_ang < 1 || O.o.p_s > 16 || O.o.p_ang > 16) return 1;
   int rc = O.run(leaf_size, out);
   if (info) {
@@ -662,15 +701,16 @@ extern "C" int oracle_ifgf(const double* pts, int64_t n, const double* dens,
 // sources (near field plus cousins of levels D..3) makes this N for every x.
 extern "C" int oracle_partition_counts(const double* pts, int64_t n,
                                        double kappa, double leaf_size,
-                                       int levels, int64_t* counts) {
-  if (n < 2 || !(kappa > 0)) return 1;
+                                       const int* opts, const double* dopts,
+                                       int64_t* counts) {
+  if (n < 2) return 1;
   Oracle O;
   O.n = n;
   O.x_user = pts;
   std::vector<double> zero(2 * n, 0.0);
   O.a_user = zero.data();
   O.kappa = kappa;
-  O.o = Options{1, 1, 1, 2, 4, levels, 0, 0};
+  if (!read_options(O.o, opts, dopts, kappa, leaf_size)) return 1;
   O.build_tree(leaf_size);
   std::vector<int64_t> cnt(n, 0);
   int D = O.D;
@@ -720,16 +760,19 @@ extern "C" int oracle_interp_eval(int p_s, int p_ang, const double* values,
 // + gamma (boxes numbered in Morton order).  Returns the number of keys
 // (writing at most cap of them), or -1 on invalid input.
 extern "C" int64_t oracle_cone_keys(const double* pts, int64_t n, double kappa,
-                                    double leaf_size, const int* opts, int d,
-                                    uint64_t* out, int64_t cap) {
-  if (n < 2 || !(kappa > 0) || !(leaf_size > 0)) return -1;
+                                    double leaf_size, const int* opts,
+                                    const double* dopts, int d, uint64_t* out,
+                                    int64_t cap) {
+  if (n < 2) return -1;
   Oracle O;
   O.n = n;
   O.x_user = pts;
   std::vector<double> zero(2 * n, 0.0);
   O.a_user = zero.data();
   O.kappa = kappa;
-  O.o = Options{opts[0], opts[1], opts[2], opts[3], opts[4], opts[5], 0, 0};
+  if (!read_options(O.o, opts, dopts, kappa, leaf_size)) return -1;
+  O.o.mode = 0;
+  O.o.stages = 0;
   O.P = O.o.p_s * O.o.p_ang * O.o.p_ang;
   O.t_s.resize(O.o.p_s);
   O.t_a.resize(O.o.p_ang);

@@ -23,13 +23,27 @@ def hipcc() -> str:
     return os.path.join(rocm, "bin", "hipcc")
 
 
+def build_id() -> str:
+    """Hash of the library sources: identifies a build in the tuning cache."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)) + [os.path.join("..", "..", "include", "ifgf.h")]:
+        path = os.path.join(CSRC, name)
+        if os.path.isfile(path):
+            h.update(name.encode())
+            h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose: bool = False) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     objs = []
+    bid = build_id()
     for src in SOURCES:
         obj = os.path.join(objdir, src + ".o")
-        cmd = [hipcc()] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"),
+        cmd = [hipcc()] + HIPCC_FLAGS + [f'-DIFGF_BUILD_ID="{bid}"',
+                                          "-I", os.path.join(ROOT, "include"),
                                           "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)

@@ -65,12 +65,19 @@ static inline uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
 }
 
 int build_instance(const double* pts, int64_t n, double kappa,
-                   double leaf_size, int levels, InstanceTree& t,
-                   std::string& msg) {
+                   const LevelRule& rule, InstanceTree& t, std::string& msg) {
   if (n < 2) { msg = "need at least 2 points"; return IFGF_EINVAL; }
   if (n >= (int64_t(1) << 31)) { msg = "N >= 2^31"; return IFGF_EUNSUPPORTED; }
-  if (!(kappa > 0) || !std::isfinite(kappa)) { msg = "kappa must be > 0"; return IFGF_EINVAL; }
-  if (!(leaf_size > 0) || !std::isfinite(leaf_size)) { msg = "leaf_size must be > 0"; return IFGF_EINVAL; }
+  if (!(kappa >= 0) || !std::isfinite(kappa)) { msg = "kappa must be finite and >= 0"; return IFGF_EINVAL; }
+  if (!(rule.leaf_abs >= 0) || !std::isfinite(rule.leaf_abs) || !(rule.leaf_max >= 0) ||
+      !std::isfinite(rule.leaf_max)) {
+    msg = "leaf_abs and leaf_max must be finite and >= 0";
+    return IFGF_EINVAL;
+  }
+  if (rule.levels == 0 && rule.leaf_abs == 0) {
+    if (!(kappa > 0)) { msg = "kappa = 0 needs levels or leaf_abs (no wavelength)"; return IFGF_EINVAL; }
+    if (!(rule.leaf_size > 0) || !std::isfinite(rule.leaf_size)) { msg = "leaf_size must be > 0"; return IFGF_EINVAL; }
+  }
   double lo[3], hi[3];
   for (int a = 0; a < 3; ++a) { lo[a] = pts[a]; hi[a] = pts[a]; }
   for (int64_t i = 0; i < n; ++i)
@@ -86,11 +93,19 @@ int build_instance(const double* pts, int64_t n, double kappa,
   t.H1 = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2]));
   if (!(t.H1 > 0)) { msg = "all points coincide"; return IFGF_EDUPLICATE; }
   for (int a = 0; a < 3; ++a) t.corner[a] = 0.5 * (lo[a] + hi[a]) - 0.5 * t.H1;
-  if (levels > 0) {
-    t.D = levels;
+  if (rule.levels > 0) {
+    t.D = rule.levels;
+  } else if (rule.leaf_abs > 0) {
+    t.D = std::max(3, 1 + (int)std::llround(std::log2(t.H1 / rule.leaf_abs)));
   } else {
     double lambda = 2.0 * kPi / kappa;
-    t.D = std::max(3, 1 + (int)std::llround(std::log2(t.H1 / (leaf_size * lambda))));
+    t.D = std::max(3, 1 + (int)std::llround(std::log2(t.H1 / (rule.leaf_size * lambda))));
+  }
+  // Leaf-side cap (per-instance accuracy control): one more level while the
+  // leaf is wider than leaf_max wavelengths.
+  if (rule.levels == 0 && rule.leaf_max > 0 && kappa > 0) {
+    double lambda = 2.0 * kPi / kappa;
+    while (t.D < 21 && std::ldexp(t.H1, -(t.D - 1)) > rule.leaf_max * lambda) ++t.D;
   }
   if (t.D < 3) { msg = "levels must be >= 3"; return IFGF_EINVAL; }
   if (t.D > 21) { msg = "more than 21 levels"; return IFGF_EUNSUPPORTED; }

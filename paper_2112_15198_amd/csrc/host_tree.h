@@ -71,10 +71,20 @@ struct Merged {
   int64_t near_pairs = 0;
 };
 
+// How the number of levels D of an instance is chosen: `levels` if > 0,
+// else D = max(3, 1 + round(log2(H_1 / w))) with w = leaf_abs if > 0, else
+// w = leaf_size wavelengths; then, when leaf_max > 0 and kappa > 0, D grows
+// while the leaf side H_1 / 2^(D-1) exceeds leaf_max wavelengths.
+struct LevelRule {
+  int levels = 0;
+  double leaf_size = 0.25;
+  double leaf_max = 0;
+  double leaf_abs = 0;
+};
+
 // Returns 0 on success, else an ifgf_status code; msg receives details.
 int build_instance(const double* pts, int64_t n, double kappa,
-                   double leaf_size, int levels, InstanceTree& t,
-                   std::string& msg);
+                   const LevelRule& rule, InstanceTree& t, std::string& msg);
 
 void build_lists(InstanceTree& t, int threads);
 

@@ -11,6 +11,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -50,6 +52,8 @@ struct HipError {
 struct ifgf_plan_s {
   int p_s = 0, p_ang = 0;
   ifgf_opts opts{};
+  bool grid_doubling = true;  // the cone grid doubles per level up
+  std::string tune_cache;     // copy of opts.tune_cache
   Merged m;
   ifgf_info info{};
   // Device state.
@@ -123,6 +127,7 @@ static ifgf_status validate(int p_s, int p_ang, const ifgf_opts& o) {
   if (o.lookup < 0 || o.lookup > 1) return fail(IFGF_EINVAL, "lookup must be 0 or 1");
   if (!(o.cone_margin >= 0.0 && o.cone_margin < 0.25))
     return fail(IFGF_EINVAL, "cone_margin must be in [0, 0.25)");
+  if (o.grid_rule < 0 || o.grid_rule > 2) return fail(IFGF_EINVAL, "grid_rule must be 0, 1 or 2");
   bool ok = (p_s == 3 && p_ang == 5) || (p_s == 2 && p_ang == 3) || (p_s == 5 && p_ang == 7);
   if (!ok && !o.host_only)
     return fail(IFGF_EUNSUPPORTED, "no kernel compiled for this (p_s, p_ang)");
@@ -152,14 +157,120 @@ static void cheb_nodes(int n, double* t, double* w) {
   }
 }
 
+#ifndef IFGF_BUILD_ID
+#define IFGF_BUILD_ID "unversioned"
+#endif
+
+// Key of a plan in the tuning cache: the library build (a hash of its
+// sources), the GPU architecture, precision, RHS count, interpolation order
+// and a hash of the plan's shape (points, instances, and per step the
+// boxes, relevant cones, grid and propagation chunk counts).
+static std::string tune_key(ifgf_plan_s* P) {
+  uint64_t h = 1469598103934665603ull;  // FNV-1a, 64 bit
+  auto mix = [&](uint64_t v) {
+    for (int i = 0; i < 8; ++i) {
+      h ^= (v >> (8 * i)) & 0xffu;
+      h *= 1099511628211ull;
+    }
+  };
+  mix((uint64_t)P->m.n);
+  mix((uint64_t)P->m.n_inst);
+  mix((uint64_t)P->A.n_steps);
+  for (const StepDev& S : P->steps_h) {
+    mix((uint64_t)S.nb);
+    mix((uint64_t)S.ncones);
+    mix((uint64_t)S.ngrid);
+    mix((uint64_t)S.nchunks);
+    mix((uint64_t)S.nschunks);
+    mix((uint64_t)S.nmchunks);
+  }
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, P->device) == hipSuccess) arch = prop.gcnArchName;
+  for (char& c : arch)
+    if (c == ' ' || c == '|') c = '_';
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "%s %s prec=%d rhs=%d p=%d,%d shape=%016llx", IFGF_BUILD_ID,
+                arch.c_str(), P->opts.precision, P->opts.n_rhs, P->p_s, P->p_ang,
+                (unsigned long long)h);
+  return buf;
+}
+
+// Kernels recorded for this plan's key in the tuning cache file, one per
+// step ("-" where not tuned); false when the file has no such line.
+static bool tune_cache_read(const std::string& path, const std::string& key,
+                            std::vector<int>& modes) {
+  std::FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return false;
+  char line[4096];
+  bool found = false;
+  while (!found && std::fgets(line, sizeof(line), f)) {
+    std::string ln(line);
+    size_t bar = ln.find(" | modes=");
+    if (bar == std::string::npos || ln.compare(0, bar, key) != 0 || bar != key.size()) continue;
+    std::vector<int> got;
+    const char* p = ln.c_str() + bar + 9;
+    while (*p && *p != '\n' && *p != ' ') {
+      if (*p == '-') {
+        got.push_back(-1);
+        ++p;
+      } else {
+        char* e = nullptr;
+        long v = std::strtol(p, &e, 10);
+        if (e == p) break;
+        got.push_back((int)v);
+        p = e;
+      }
+      if (*p == ',') ++p;
+    }
+    if (got.size() == modes.size()) {
+      modes = got;
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+static void tune_cache_append(const std::string& path, const std::string& key,
+                              const std::vector<int>& modes) {
+  std::FILE* f = std::fopen(path.c_str(), "a");
+  if (!f) return;  // an unwritable cache only costs the next plan a re-tune
+  std::string ln = key + " | modes=";
+  for (size_t i = 0; i < modes.size(); ++i) {
+    if (i) ln += ",";
+    ln += modes[i] < 0 ? std::string("-") : std::to_string(modes[i]);
+  }
+  ln += "\n";
+  std::fputs(ln.c_str(), f);
+  std::fclose(f);
+}
+
 // Time the four propagation kernels on every level where the matrix-core
 // forms apply (zeroed cone values: the kernels' work does not depend on the
-// values) and keep the fastest.
+// values) and keep the fastest.  With a tuning cache, a recorded choice for
+// the same key is taken without timing.
 static void autotune(ifgf_plan_s* P) {
   ApplyArgs& A = P->A;
   hipStream_t st = P->stream;
   const int PP = P->p_s * P->p_ang * P->p_ang;
   if (PP > kMfmaMaxP) return;
+  std::string key;
+  if (!P->tune_cache.empty()) {
+    key = tune_key(P);
+    std::vector<int> modes(A.n_steps, -1);
+    if (tune_cache_read(P->tune_cache, key, modes)) {
+      for (int l = 1; l < A.n_steps; ++l) {
+        StepDev& Q = P->steps_h[l];
+        if (modes[l] >= kPropNode && modes[l] <= kPropMedium && Q.ncones > 0 && Q.nchunks > 0)
+          Q.prop_grouped = modes[l];
+      }
+      P->info.tune_cache_hit = 1;
+      HIP_TRY(hipMemcpy(P->steps_d, P->steps_h.data(), sizeof(StepDev) * A.n_steps,
+                        hipMemcpyHostToDevice));
+      return;
+    }
+  }
   size_t csize = P->opts.precision == IFGF_FP64 ? 16 : 8;
   int64_t maxc = 1;
   for (int l = 0; l < A.n_steps; ++l) maxc = std::max<int64_t>(maxc, P->steps_h[l].ncones);
@@ -188,6 +299,14 @@ static void autotune(ifgf_plan_s* P) {
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  if (!P->tune_cache.empty()) {
+    std::vector<int> modes(A.n_steps, -1);
+    for (int l = 1; l < A.n_steps; ++l) {
+      const StepDev& Q = P->steps_h[l];
+      if (Q.ncones > 0 && Q.nchunks > 0) modes[l] = Q.prop_grouped;
+    }
+    tune_cache_append(P->tune_cache, key, modes);
+  }
   HIP_TRY(hipMemcpy(P->steps_d, P->steps_h.data(), sizeof(StepDev) * A.n_steps,
                     hipMemcpyHostToDevice));
 }
@@ -231,10 +350,12 @@ static void build_device(ifgf_plan_s* P) {
     D.pt_box = P->upload(S.pt_box);
     D.inst_h = P->upload(S.inst_h);
     D.inst_H = P->upload(S.inst_H);
-    // Cone grid: leaf grid doubled per dimension for every level up.
-    D.ns = P->opts.leaf_grid[0] << l;
-    D.nt = P->opts.leaf_grid[1] << l;
-    D.np = P->opts.leaf_grid[2] << l;
+    // Cone grid: the leaf grid, doubled per dimension for every level up
+    // when it follows the wavelength (grid_rule).
+    const int gs = P->grid_doubling ? l : 0;
+    D.ns = P->opts.leaf_grid[0] << gs;
+    D.nt = P->opts.leaf_grid[1] << gs;
+    D.np = P->opts.leaf_grid[2] << gs;
     D.ngrid = (int64_t)D.ns * D.nt * D.np;
     D.ds = eta / D.ns;
     D.dt = kPi / D.nt;
@@ -466,12 +587,14 @@ static void fill_info(ifgf_plan_s* P) {
     for (int64_t b = 0; b < m.step[l].nb; ++b)
       pairs += (m.step[l].cous_begin[b + 1] - m.step[l].cous_begin[b]) * (int64_t)m.step[l].count[b];
     I.cousin_pairs[l] = pairs;
-    I.grid[l] = (int64_t)(P->opts.leaf_grid[0] << l) * (P->opts.leaf_grid[1] << l) *
-                (P->opts.leaf_grid[2] << l);
+    const int gs = P->grid_doubling ? l : 0;
+    I.grid[l] = (int64_t)(P->opts.leaf_grid[0] << gs) * (P->opts.leaf_grid[1] << gs) *
+                (P->opts.leaf_grid[2] << gs);
     I.prop_mode[l] = (l >= 1 && P->device_ready) ? P->steps_h[l].prop_grouped + 1 : 0;
   }
   I.near_pairs = m.near_pairs;
   I.device_bytes = P->bytes;
+  I.grid_doubling = P->grid_doubling ? 1 : 0;
 }
 
 static ifgf_status plan_common(ifgf_plan_t* out, int n_inst,
@@ -495,18 +618,48 @@ static ifgf_status plan_common(ifgf_plan_t* out, int n_inst,
   if (offsets[0] != 0) return fail(IFGF_EINVAL, "offsets[0] must be 0");
   for (int i = 0; i < n_inst; ++i)
     if (offsets[i + 1] - offsets[i] < 2) return fail(IFGF_EINVAL, "every instance needs >= 2 points");
+  // Cone grid rule: doubling follows the wavelength; kappa = 0 keeps the
+  // leaf grid.  Instances of one plan share the grid of every step.
+  int n_zero = 0;
+  for (int i = 0; i < n_inst; ++i) n_zero += kappas[i] == 0.0;
+  if (o.grid_rule == 0 && n_zero > 0 && n_zero < n_inst)
+    return fail(IFGF_EINVAL, "grid_rule 0 cannot mix kappa = 0 and kappa > 0 in one plan");
   ifgf_plan_s* P = new (std::nothrow) ifgf_plan_s();
   if (!P) return fail(IFGF_ENOMEM, "out of host memory");
   P->p_s = p_s;
   P->p_ang = p_ang;
   P->opts = o;
+  P->grid_doubling = o.grid_rule == 1 || (o.grid_rule == 0 && n_zero == 0);
+  if (o.tune_cache) P->tune_cache = o.tune_cache;
+  P->opts.tune_cache = nullptr;  // the plan keeps its own copy
   try {
+    // Points may be host or device memory; device points are copied to the
+    // host, where the octree is built.
+    std::vector<double> host_pts;
+    if (!o.host_only) {
+      hipPointerAttribute_t attr;
+      std::memset(&attr, 0, sizeof(attr));
+      hipError_t pe = hipPointerGetAttributes(&attr, points);
+      if (pe == hipSuccess && attr.type == hipMemoryTypeDevice) {
+        host_pts.resize(3 * (size_t)offsets[n_inst]);
+        HIP_TRY(hipMemcpy(host_pts.data(), points, sizeof(double) * host_pts.size(),
+                          hipMemcpyDeviceToHost));
+        points = host_pts.data();
+      } else if (pe != hipSuccess) {
+        (void)hipGetLastError();  // unregistered host memory: not an error
+      }
+    }
+    LevelRule rule;
+    rule.levels = o.levels;
+    rule.leaf_size = leaf_size;
+    rule.leaf_max = o.leaf_max;
+    rule.leaf_abs = o.leaf_abs;
     std::vector<InstanceTree> trees(n_inst);
     int threads = default_threads();
     for (int i = 0; i < n_inst; ++i) {
       std::string msg;
       int rc = build_instance(points + 3 * offsets[i], offsets[i + 1] - offsets[i],
-                              kappas[i], leaf_size, o.levels, trees[i], msg);
+                              kappas[i], rule, trees[i], msg);
       if (rc != IFGF_OK) {
         delete P;
         return fail((ifgf_status)rc, n_inst > 1 ? "instance " + std::to_string(i) + ": " + msg : msg);

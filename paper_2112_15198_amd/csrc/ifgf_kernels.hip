@@ -766,12 +766,6 @@ prop_mfma_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc
         }
       }
       __syncthreads();
-#ifdef IFGF_BREUSE
-      // Work items (child cone k, N-tile): the B tile is loaded once and
-      // used for every M-tile of k.
-      for (int item = wave; item < na * ntn; item += NWAVES) {
-        const int k = item / ntn, nt = item - (item / ntn) * ntn;
-#else
       // M-tiles of all child cones of this octant, enumerated in order.
       int nmt = 0;
       for (int k = 0; k < na; ++k)
@@ -786,7 +780,6 @@ prop_mfma_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc
           mt0 -= t;
           ++k;
         }
-#endif
         const int rb0 = s_rbeg[o * (P + 1) + k], rlen = s_rbeg[o * (P + 1) + k + 1] - rb0;
         const int col = nt * 16 + (lane & 15);
         const bool colok = col < ncols;
@@ -810,12 +803,8 @@ prop_mfma_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc
           bi[kk] = x.y;
         }
         const int b = s_nlist[o * CB + n];
-#ifdef IFGF_BREUSE
-        for (int mt = 0; mt * 16 < rlen; ++mt) {
-#else
         {
           const int mt = mt0;
-#endif
           // A operand: lane holds W[row 16 mt + lane % 16][4 kk + kq].
           const int arow = min(rb0 + mt * 16 + (lane & 15), P - 1);
           const T4* ap = reinterpret_cast<const T4*>(s_A + arow * RS + kq * KS);

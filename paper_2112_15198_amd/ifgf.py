@@ -36,7 +36,9 @@ class Opts(ctypes.Structure):
                 ("stages", ctypes.c_int), ("host_only", ctypes.c_int),
                 ("device", ctypes.c_int), ("stream", ctypes.c_void_p),
                 ("prop_kernel", ctypes.c_int), ("lookup", ctypes.c_int),
-                ("autotune", ctypes.c_int), ("cone_margin", ctypes.c_double)]
+                ("autotune", ctypes.c_int), ("cone_margin", ctypes.c_double),
+                ("leaf_max", ctypes.c_double), ("leaf_abs", ctypes.c_double),
+                ("grid_rule", ctypes.c_int), ("tune_cache", ctypes.c_char_p)]
 
 
 class Info(ctypes.Structure):
@@ -53,7 +55,8 @@ class Info(ctypes.Structure):
                 ("autotune_ms", (ctypes.c_float * 4) * IFGF_MAX_LEVELS),
                 ("leaf_pairs", ctypes.c_int64),
                 ("near_pairs", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("plan_seconds", ctypes.c_double)]
+                ("plan_seconds", ctypes.c_double), ("tune_cache_hit", ctypes.c_int),
+                ("grid_doubling", ctypes.c_int)]
 
 
 class StageTimes(ctypes.Structure):
@@ -110,8 +113,12 @@ def _check(rc):
         raise IFGFError(rc, load_library().ifgf_status_string(rc).decode())
 
 
+GRID_RULES = {"auto": 0, "double": 1, "constant": 2, 0: 0, 1: 1, 2: 2}
+
+
 def _opts(precision, n_rhs, leaf_grid, levels, stages, host_only, device,
-          cone_margin=None, prop_kernel=0, lookup=0, autotune=False):
+          cone_margin=None, prop_kernel=0, lookup=0, autotune=False,
+          leaf_max=0.0, leaf_abs=0.0, grid_rule="auto", tune_cache=None):
     o = Opts()
     _check(load_library().ifgf_default_opts(ctypes.byref(o)))
     o.precision = {"fp64": FP64, "fp32": FP32_MIXED, "mixed": FP32_MIXED,
@@ -129,6 +136,11 @@ def _opts(precision, n_rhs, leaf_grid, levels, stages, host_only, device,
                      0: 0, 1: 1, 2: 2, 3: 3, 4: 4}[prop_kernel]
     o.lookup = {"auto": 0, "hash": 1, 0: 0, 1: 1}[lookup]
     o.autotune = 1 if autotune else 0
+    o.leaf_max = float(leaf_max)
+    o.leaf_abs = float(leaf_abs)
+    o.grid_rule = GRID_RULES[grid_rule] if grid_rule in GRID_RULES else int(grid_rule)
+    # The plan copies the path at plan time.
+    o.tune_cache = None if not tune_cache else os.fsencode(tune_cache)
     return o
 
 
@@ -150,11 +162,16 @@ class Plan:
         import torch
         return torch.complex128 if self.precision == FP64 else torch.complex64
 
-    def apply(self, dens, out=None, check=False, graph=False):
+    def apply(self, dens, out=None, check=None, graph=False):
         """dens: CUDA tensor (n_rhs, N) or (N,) of the plan's complex dtype.
 
         graph=True replays a HIP graph of the whole apply, captured on the
-        first call for this (dens, out) pair."""
+        first call for this (dens, out) pair.  check (default: True for an
+        eager apply, False for a graph replay) waits for the apply and
+        raises IFGFError(IFGF_ELOOKUP) if a cone look-up missed; with
+        check=False call check() before trusting the result."""
+        if check is None:
+            check = not graph
         import torch
         if self._h is None:
             raise ValueError("plan is closed")
@@ -189,7 +206,8 @@ class Plan:
                 "prop_mode": list(inf.prop_mode[:L]),
                 "autotune_ms": [tuple(inf.autotune_ms[l]) for l in range(L)],
                 "near_pairs": inf.near_pairs, "device_bytes": inf.device_bytes,
-                "plan_seconds": inf.plan_seconds}
+                "plan_seconds": inf.plan_seconds, "tune_cache_hit": bool(inf.tune_cache_hit),
+                "grid_doubling": bool(inf.grid_doubling)}
 
     def profile(self, enable=True):
         """Time every kernel launch of later applies with HIP events."""
@@ -232,33 +250,53 @@ class Plan:
         self.close()
 
 
+def _points_arg(points):
+    """(pointer, N, keep-alive) of an (N, 3) float64 array: a numpy array
+    (host) or a contiguous CUDA tensor (device)."""
+    if hasattr(points, "is_cuda") and points.is_cuda:
+        import torch
+        if points.dtype != torch.float64 or points.dim() != 2 or points.shape[1] != 3:
+            raise ValueError("device points must be a float64 tensor of shape (N, 3)")
+        t = points.contiguous()
+        return ctypes.c_void_p(t.data_ptr()), t.shape[0], t
+    pts = np.ascontiguousarray(np.asarray(points, dtype=np.float64))
+    if pts.ndim != 2 or pts.shape[1] != 3:
+        raise ValueError("points must have shape (N, 3)")
+    return pts.ctypes.data_as(ctypes.c_void_p), pts.shape[0], pts
+
+
 def plan(points, kappa, p_s=3, p_ang=5, leaf_size=0.25, precision="fp64",
          n_rhs=1, leaf_grid=(2, 4, 8), levels=0, stages=3, host_only=False,
          device=None, cone_margin=None, prop_kernel="auto", lookup="auto",
-         autotune=False):
-    """Plan one instance; points is an (N, 3) float64 array (host).
+         autotune=False, leaf_max=0.0, leaf_abs=0.0, grid_rule="auto",
+         tune_cache=None):
+    """Plan one instance; points is an (N, 3) float64 array on the host or a
+    float64 CUDA tensor.
 
     precision: "fp64" (IFGF_FP64, complex128 densities), "fp32"
     (IFGF_FP32_MIXED, complex64) or "bf16x3" (IFGF_FP32_BF16X3, complex64:
     FP32-mixed with the wave-task propagation product in three-term BF16
     form).  prop_kernel: "auto", "node", "grouped", "small" (one-wave) or
-    "medium" (four-wave); autotune=True times the four per level instead."""
-    pts = np.ascontiguousarray(np.asarray(points, dtype=np.float64))
-    if pts.ndim != 2 or pts.shape[1] != 3:
-        raise ValueError("points must have shape (N, 3)")
+    "medium" (four-wave); autotune=True times the four per level instead
+    (tune_cache: a file that keeps the choices across plans).  kappa = 0
+    (the Laplace kernel) needs leaf_abs (leaf side in length units) or
+    levels; leaf_max caps the leaf side in wavelengths."""
+    ptr, n, keep = _points_arg(points)
     o = _opts(precision, n_rhs, leaf_grid, levels, stages, host_only, device,
-              cone_margin, prop_kernel, lookup, autotune)
+              cone_margin, prop_kernel, lookup, autotune, leaf_max, leaf_abs,
+              grid_rule, tune_cache)
     h = ctypes.c_void_p()
-    _check(load_library().ifgf_plan_ex(ctypes.byref(h), pts.ctypes.data_as(ctypes.c_void_p),
-                                       pts.shape[0], float(kappa), int(p_s), int(p_ang),
-                                       float(leaf_size), ctypes.byref(o)))
-    return Plan(h, pts.shape[0], o.n_rhs, o.precision)
+    _check(load_library().ifgf_plan_ex(ctypes.byref(h), ptr, n, float(kappa), int(p_s),
+                                       int(p_ang), float(leaf_size), ctypes.byref(o)))
+    del keep
+    return Plan(h, n, o.n_rhs, o.precision)
 
 
 def plan_batched(points_list, kappas, p_s=3, p_ang=5, leaf_size=0.25,
                  precision="fp64", n_rhs=1, leaf_grid=(2, 4, 8), levels=0,
                  stages=3, host_only=False, device=None, cone_margin=None,
-                 prop_kernel="auto", lookup="auto", autotune=False):
+                 prop_kernel="auto", lookup="auto", autotune=False, leaf_max=0.0,
+                 leaf_abs=0.0, grid_rule="auto", tune_cache=None):
     """Plan several independent instances evaluated together by each apply.
 
     Densities and outputs are (n_rhs, sum N_i), instances concatenated.
@@ -269,7 +307,8 @@ def plan_batched(points_list, kappas, p_s=3, p_ang=5, leaf_size=0.25,
     offsets[1:] = np.cumsum([len(p) for p in points_list])
     kap = np.ascontiguousarray(np.asarray(kappas, dtype=np.float64))
     o = _opts(precision, n_rhs, leaf_grid, levels, stages, host_only, device,
-              cone_margin, prop_kernel, lookup, autotune)
+              cone_margin, prop_kernel, lookup, autotune, leaf_max, leaf_abs,
+              grid_rule, tune_cache)
     h = ctypes.c_void_p()
     _check(load_library().ifgf_plan_batched(
         ctypes.byref(h), len(points_list), offsets.ctypes.data_as(ctypes.c_void_p),

@@ -88,6 +88,11 @@ def _instance(name, pts, kappa, n_rhs, seed, n_samples):
                     {"N": n, "n_rhs": n_rhs, "seed": seed})
 
 
+# Leaf-side cap (wavelengths) with which the 48-instance batch is planned:
+# its arbitrary sizes round to leaves of 0.18-0.35 wavelengths, and the cap
+# gives the ten widest one more level.
+BATCH_LEAF_MAX = 0.3
+
 # The workloads.  Keys name what each workload is.
 WORKLOADS = {
     # N=5,024 unit-sphere lattice, kappa = 4 pi (4 wavelengths across).

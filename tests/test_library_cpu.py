@@ -54,6 +54,45 @@ def test_host_tree_matches_oracle_tree(geom):
     np.testing.assert_array_equal(cnt, oracle.partition_counts(p, k))
 
 
+@pytest.mark.parametrize("rule", ["leaf_max", "leaf_abs", "laplace"])
+def test_host_level_rules_match_oracle(rule):
+    """The level rules (leaf-side cap in wavelengths; absolute leaf side, the
+    rule for kappa = 0) give the oracle's D and boxes, and the partition of
+    the sources."""
+    n = 4373
+    p = W.spheroid(n)
+    k = W.kappa_oblate_10ppw(n)
+    kw = {"leaf_max": dict(leaf_max=0.3), "leaf_abs": dict(leaf_abs=0.05),
+          "laplace": dict(leaf_abs=0.1)}[rule]
+    if rule == "laplace":
+        k = 0.0
+    pl = ifgf.plan(p, k, host_only=True, **kw)
+    info = pl.info()
+    _, oi = oracle.ifgf(p, np.zeros(n), k, far=False, return_info=True, **kw)
+    assert info["D"] == oi["D"]
+    assert info["boxes"] == oi["boxes"][2:][::-1]
+    np.testing.assert_array_equal(pl.partition_counts(), oracle.partition_counts(p, k, **kw))
+    assert info["grid_doubling"] == (k > 0)
+    if rule == "leaf_max":
+        assert info["D"] == 6
+
+
+def test_laplace_and_grid_rules_validated():
+    p = W.fibonacci_sphere(200)
+    # kappa = 0 without a wavelength-free rule, negative kappa, bad grid rule.
+    assert _status(lambda: ifgf.plan(p, 0.0, host_only=True)) == 1  # no level rule
+    assert _status(lambda: ifgf.plan(p, -2.0, leaf_abs=0.1, host_only=True)) == 1
+    assert _status(lambda: ifgf.plan(p, 3.0, grid_rule=3, host_only=True)) == 1
+    assert _status(lambda: ifgf.plan(p, 3.0, leaf_max=-1.0, host_only=True)) == 1
+    # One batched plan cannot mix kappa = 0 and kappa > 0 under the automatic
+    # grid rule; an explicit rule allows it.
+    assert _status(lambda: ifgf.plan_batched([p, p], [0.0, 3.0], leaf_abs=0.2,
+                                             host_only=True)) == 1
+    ifgf.plan_batched([p, p], [0.0, 3.0], leaf_abs=0.2, grid_rule="constant",
+                      host_only=True).close()
+    ifgf.plan(p, 0.0, levels=4, host_only=True).close()
+
+
 def test_batched_host_plan_partition():
     pts = [W.fibonacci_sphere(3000), W.spheroid(4500), W.fibonacci_sphere(800)]
     kap = [W.kappa_sphere_10ppw(3000), W.kappa_oblate_10ppw(4500), 9.0]
@@ -74,7 +113,7 @@ def test_error_codes():
     p = W.fibonacci_sphere(100)
     assert _status(lambda: ifgf.plan(p[:1], 3.0, host_only=True)) == 1
     assert _status(lambda: ifgf.plan(p, -1.0, host_only=True)) == 1
-    assert _status(lambda: ifgf.plan(p, 0.0, host_only=True)) == 1
+    assert _status(lambda: ifgf.plan(p, 0.0, host_only=True)) == 1  # no level rule
     q = p.copy()
     q[7, 1] = np.nan
     assert _status(lambda: ifgf.plan(q, 3.0, host_only=True)) == 1

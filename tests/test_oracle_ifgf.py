@@ -144,3 +144,88 @@ def test_levels_from_leaf_size():
     assert info["D"] == 5
     _, info = oracle.ifgf(p, np.zeros(5024), 0.5, far=False, return_info=True)
     assert info["D"] == 3
+
+
+# ---------------------------------------------------------------------------
+# The Laplace kernel (kappa = 0) through the same factorisation: the level
+# rule takes an absolute leaf side, and the cone grid stays the leaf grid at
+# every level (the analytic factor has no wavelength; in (s, theta, phi) it
+# is the same function at every level).
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("geom", ["sphere", "oblate", "clusters"])
+def test_laplace_exact_mode_reproduces_direct_sum(geom):
+    p, _ = GEOMS[geom]()
+    a = W.densities(p.shape[0], 1, 25)[0]
+    ref = oracle.direct_sum(p, a, 0.0)
+    side = float(np.max(p.max(0) - p.min(0)))
+    ex = oracle.ifgf(p, a, 0.0, exact=True, leaf_abs=side / 16)
+    assert relerr(ex, ref) < 1e-12
+
+
+def test_laplace_tetrahedron_through_ifgf():
+    """Four vertices of a regular tetrahedron of edge L, unit densities: in
+    exact mode the IFGF tree, lists and factorisation reproduce the closed
+    form 3/(4 pi L) at every vertex; interpolated, the vertices are cousins
+    at the closest cousin distance (the interpolation's worst case) and the
+    result is within 1e-3."""
+    L = 0.7
+    import math as _m
+    p = L / 2 * np.array([[1, 0, -1 / _m.sqrt(2)], [-1, 0, -1 / _m.sqrt(2)],
+                           [0, 1, 1 / _m.sqrt(2)], [0, -1, 1 / _m.sqrt(2)]])
+    exact = 3.0 / (4.0 * _m.pi * L)
+    out = oracle.ifgf(p, np.ones(4), 0.0, leaf_abs=L / 4, exact=True)
+    np.testing.assert_allclose(out, exact, rtol=1e-14, atol=0)
+    out = oracle.ifgf(p, np.ones(4), 0.0, leaf_abs=L / 4, leaf_grid=(2, 4, 8))
+    np.testing.assert_allclose(out, exact, rtol=1e-3, atol=0)
+
+
+def test_laplace_accuracy_and_convergence():
+    n = 4000
+    p = W.fibonacci_sphere(n)
+    a = W.densities(n, 1, 26)[0]
+    ref = oracle.direct_sum(p, a, 0.0)
+    errs = [relerr(oracle.ifgf(p, a, 0.0, p_s=ps, p_ang=pa, leaf_grid=(1, 2, 4),
+                               leaf_abs=0.25), ref)
+            for ps, pa in [(2, 3), (3, 5), (5, 7)]]
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < errs[1] / 10
+    # The default leaf grid at (3, 5) meets 1e-4.
+    res, info = oracle.ifgf(p, a, 0.0, leaf_grid=(2, 4, 8), leaf_abs=0.25,
+                            return_info=True)
+    assert relerr(res, ref) < 1e-4
+    assert info["D"] == 4
+
+
+def test_laplace_needs_a_level_rule():
+    p = W.fibonacci_sphere(500)
+    with pytest.raises(RuntimeError):
+        oracle.ifgf(p, np.ones(500), 0.0)          # no wavelength, no leaf_abs
+    out = oracle.ifgf(p, np.ones(500), 0.0, levels=4)  # explicit D is enough
+    assert np.isfinite(out).all()
+
+
+# ---------------------------------------------------------------------------
+# Per-instance accuracy control: a cap on the leaf side in wavelengths.
+# ---------------------------------------------------------------------------
+
+def test_leaf_max_adds_levels_and_lowers_the_error():
+    """The N = 4,373 spheroid of the 48-instance batch rounds to leaves of
+    0.31 wavelengths (D = 5); a 0.3-wavelength cap gives D = 6 (0.155) and a
+    smaller error against the direct sum; a cap above the leaf changes
+    nothing."""
+    n = 4373
+    p = W.spheroid(n)
+    k = W.kappa_oblate_10ppw(n)
+    a = W.densities(n, 1, 4034)[0]
+    ref = oracle.direct_sum(p, a, k)
+    r0, i0 = oracle.ifgf(p, a, k, leaf_grid=(2, 4, 8), return_info=True)
+    r1, i1 = oracle.ifgf(p, a, k, leaf_grid=(2, 4, 8), leaf_max=0.3, return_info=True)
+    r2, i2 = oracle.ifgf(p, a, k, leaf_grid=(2, 4, 8), leaf_max=0.4, return_info=True)
+    lam = 2 * math.pi / k
+    assert i0["D"] == 5 and i1["D"] == 6 and i2["D"] == 5
+    assert i0["H1"] / 2 ** 4 > 0.3 * lam >= i1["H1"] / 2 ** 5
+    np.testing.assert_array_equal(r2, r0)
+    assert relerr(r1, ref) < relerr(r0, ref)
+    # The partition of the sources holds on the deeper tree too.
+    assert (oracle.partition_counts(p, k, leaf_max=0.3) == n).all()
