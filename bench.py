@@ -22,9 +22,22 @@ Prints one JSON line:
   roofline   = the dominant kernel: algorithmic FLOP per launch over its
                mean HIP-event launch time (eager applies), against the
                MI355X peak of its precision (matrix cores for the
-               matrix-core propagation, vector ALUs otherwise)
+               matrix-core propagation, vector ALUs otherwise).  FLOP per
+               unit and RHS: 380 per (parent-cone node, relevant child) of
+               the propagation (a 75-term complex-by-real tensor contraction
+               in sum-factorised form, 186 FMA, plus the Lagrange basis and
+               the complex ratio), 490 per (target, cousin box) of the
+               interpolation, 25 per (leaf-cone node, source) and 20 per
+               near-field pair (transcendentals not counted)
   cpu_baseline = the CPU oracle (FP64 direct sum, OpenMP) on the sampled
                targets, scaled to N^2/s
+  cpu_baseline_ifgf = the CPU oracle's plain FP64 IFGF (OpenMP) on a
+               smaller sphere, with the GPU paths timed on the same sphere
+  cpu        = the host the CPU legs ran on (model, logical CPUs, OpenMP
+               threads used)
+  configs    = compact records of the other workloads (default kernel
+               choice, fewer applies): ms, N^2/t, plan time and the error
+               against the FP64 direct sum on a stated sample of targets
 """
 from __future__ import annotations
 
@@ -50,11 +63,16 @@ PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "bf16x3": 157.3}
 PEAK_BF16X3_PRODUCT = 2500.0 / 3
 
 
-def flops_per_eval(P):
-    """Algorithmic FLOP of one interpolant evaluation times one complex
-    factor, per right-hand side: P complex-by-real multiply-adds of the
-    tensor contraction (4 FLOP each) plus one complex multiply-add (8)."""
-    return 4 * P + 8
+# Algorithmic FLOP per unit and right-hand side, (P_s, P_ang) = (3, 5).
+FLOP_PROP = 380      # (parent-cone node, relevant child)
+FLOP_INTERP = 490    # (target, cousin box): contraction, FP64 r and phase
+FLOP_LEAF = 25       # (leaf-cone node, source)
+FLOP_NEAR = 20       # (target, source) pair
+
+
+def flop_scale(P):
+    """The counts above are for P = 75 nodes; other orders scale with P."""
+    return P / 75.0
 
 
 def measured_traffic(stage, workload, precision):
@@ -107,6 +125,152 @@ def stage_times(pl, a, steps):
     return st
 
 
+def cpu_info():
+    """The host the CPU legs run on."""
+    import oracle
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = None
+    return {"model": model, "logical_cpus": os.cpu_count(), "cpus_allowed": affinity,
+            "omp_threads": oracle.threads()}
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def time_plan(pl, a, steps, warmup):
+    """Mean ms per captured-graph apply, and the output."""
+    ms, out = time_applies(pl, a, steps, warmup, graph=True)
+    return ms, out.cpu().numpy().astype(np.complex128)
+
+
+def cpu_ifgf_leg(n, steps, warmup):
+    """The oracle's plain FP64 IFGF (OpenMP, all threads) on an N-point unit
+    sphere at ~10 points per wavelength, its error against the FP64 direct
+    sum on every target, and the GPU FP32-mixed and FP64 applies of the same
+    sphere timed beside it."""
+    import torch
+    import oracle
+    import paper_2112_15198_amd as ifgf
+    from paper_2112_15198_amd import workloads as W
+    pts = W.fibonacci_sphere(n)
+    kappa = W.kappa_sphere_10ppw(n)
+    dens = W.densities(n, 1, 1010)
+    print(f"# cpu ifgf: oracle on sphere N={n}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    o, oi = oracle.ifgf(pts, dens[0], kappa, leaf_grid=(2, 4, 8), return_info=True)
+    wall = time.perf_counter() - t0
+    ref = oracle.direct_sum(pts, dens[0], kappa)
+    rec = {"kind": "oracle IFGF", "N": n, "kappa": kappa, "D": oi["D"],
+           "precision": "fp64", "threads": oracle.threads(),
+           "apply_s": oi["eval_s"], "setup_s": oi["setup_s"], "wall_s": wall,
+           "value": float(n) ** 2 / oi["eval_s"], "unit": "N^2/s",
+           "rel_err_vs_direct_sum": relerr(o, ref),
+           "sample": "all N targets; apply = near field, leaf evaluations, interpolation "
+                     "and propagation (set-up timed apart)"}
+    for prec in ("fp32", "fp64"):
+        pl = ifgf.plan(pts, kappa, precision=prec, leaf_grid=(2, 4, 8))
+        dt = torch.complex128 if prec == "fp64" else torch.complex64
+        a = torch.from_numpy(dens).to(dt).cuda()
+        ms, g = time_plan(pl, a, steps, warmup)
+        pl.close()
+        rec["gpu_" + prec] = {"ms": ms, "value": float(n) ** 2 / (ms * 1e-3),
+                              "rel_err_vs_direct_sum": relerr(g[0], ref),
+                              "rel_err_vs_oracle_ifgf": relerr(g[0], o)}
+        rec["gpu_" + prec]["speedup_vs_oracle_ifgf"] = oi["eval_s"] * 1e3 / ms
+    print(f"# cpu ifgf: oracle {oi['eval_s']:.2f} s apply ({wall:.1f} s with set-up); "
+          f"GPU fp32 {rec['gpu_fp32']['ms']:.3f} ms, fp64 {rec['gpu_fp64']['ms']:.3f} ms",
+          file=sys.stderr, flush=True)
+    return rec
+
+
+# The other workloads, as compact records: (record, workload, precisions,
+# sampled targets per instance for the error; None = the workload's own).
+CONFIG_RUNS = [
+    ("sphere_5k", ["fp64", "fp32"], None),
+    ("oblate_1m", ["fp32"], 1024),
+    ("batch48", ["fp32"], 512),
+    ("sphere_5m", ["fp32"], 1024),
+]
+
+
+def run_configs(steps, warmup, names=None):
+    import torch
+    import oracle
+    import paper_2112_15198_amd as ifgf
+    from paper_2112_15198_amd import workloads as W
+    recs = {}
+    for name, precs, nsamp in CONFIG_RUNS:
+        if names and name not in names:
+            continue
+        w = W.make(name)
+        insts = w if isinstance(w, list) else [w]
+        n_rhs = insts[0].dens.shape[0]
+        dens = np.concatenate([x.dens for x in insts], axis=1)
+        n2 = float(sum(float(x.points.shape[0]) ** 2 for x in insts))
+        popts = W.plan_options(name)
+        rec = {"N_total": int(dens.shape[1]), "instances": len(insts), "n_rhs": n_rhs,
+               "plan_options": {k: (list(v) if isinstance(v, tuple) else v)
+                                for k, v in popts.items()},
+               "kernel_choice": "default (no autotuning)"}
+        outs = {}
+        for prec in precs:
+            print(f"# config {name} {prec}: planning", file=sys.stderr, flush=True)
+            t0 = time.perf_counter()
+            if len(insts) > 1:
+                pl = ifgf.plan_batched([x.points for x in insts], [x.kappa for x in insts],
+                                       precision=prec, n_rhs=n_rhs, **popts)
+            else:
+                pl = ifgf.plan(insts[0].points, insts[0].kappa, precision=prec,
+                               n_rhs=n_rhs, **popts)
+            plan_s = time.perf_counter() - t0
+            dt = torch.complex128 if prec == "fp64" else torch.complex64
+            a = torch.from_numpy(dens).to(dt).cuda()
+            ms, g = time_plan(pl, a, steps, warmup)
+            info = pl.info()
+            pl.close()
+            del a
+            torch.cuda.empty_cache()
+            outs[prec] = g
+            rec[prec] = {"ms": ms, "value": n2 * n_rhs / (ms * 1e-3), "unit": "N^2/s",
+                         "plan_s": plan_s, "D": info["D"]}
+            print(f"# config {name} {prec}: {ms:.3f} ms/apply, plan {plan_s:.1f} s",
+                  file=sys.stderr, flush=True)
+        # Error against the FP64 direct sum (eq. errorcomputation), max over
+        # instances and RHS.
+        errs = {p: 0.0 for p in precs}
+        off, pairs = 0, 0
+        for x in insts:
+            ni = x.points.shape[0]
+            tg = x.targets if nsamp is None else x.targets[:nsamp]
+            for r in range(n_rhs):
+                ref = oracle.direct_sum(x.points, x.dens[r], x.kappa, tg)
+                pairs += ni * len(tg)
+                for p in precs:
+                    errs[p] = max(errs[p], relerr(outs[p][r, off:off + ni][tg], ref))
+            off += ni
+        for p in precs:
+            rec[p]["rel_err"] = errs[p]
+        rec["error_sample"] = ("all targets" if nsamp is None else
+                               f"the first {nsamp} of each instance's sampled targets") + \
+            ", max over instances and RHS"
+        recs[name] = rec
+        print(f"# config {name}: rel-err " + ", ".join(f"{p} {errs[p]:.2e}" for p in precs),
+              file=sys.stderr, flush=True)
+    return recs
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,6 +288,12 @@ def main():
                          "(known bytes, for calibrating rocprofv3 FETCH/WRITE_SIZE)")
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the CPU oracle (baseline and error check)")
+    ap.add_argument("--cpu-ifgf-n", type=int, default=40000,
+                    help="sphere size of the CPU oracle IFGF leg (0: skip)")
+    ap.add_argument("--configs", default="all",
+                    help="compact records of the other workloads: all, none, or a "
+                         "comma-separated list of workload names")
+    ap.add_argument("--config-steps", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported",
@@ -150,7 +320,9 @@ def main():
     n2 = float(sum(float(x.points.shape[0]) ** 2 for x in insts))
     n_rhs = insts[0].dens.shape[0]
     dens = np.concatenate([x.dens for x in insts], axis=1)
-    p_s, p_ang, grid = 3, 5, (2, 4, 8)
+    p_s, p_ang = 3, 5
+    popts = W.plan_options(args.workload)
+    grid = popts["leaf_grid"]
     P = p_s * p_ang * p_ang
     precs = {"all": ["fp32", "fp64", "bf16x3"], "both": ["fp32", "fp64"]}.get(
         args.precision, [args.precision])
@@ -160,10 +332,10 @@ def main():
         if batch:
             pl = ifgf.plan_batched([x.points for x in insts], [x.kappa for x in insts],
                                    p_s=p_s, p_ang=p_ang, precision=prec, n_rhs=n_rhs,
-                                   leaf_grid=grid, autotune=True)
+                                   autotune=True, **popts)
         else:
             pl = ifgf.plan(w.points, w.kappa, p_s=p_s, p_ang=p_ang, precision=prec,
-                           n_rhs=n_rhs, leaf_grid=grid, autotune=True)
+                           n_rhs=n_rhs, autotune=True, **popts)
         plan_s = time.perf_counter() - t0
         print(f"# {prec}: plan {plan_s:.2f} s (N={n}, D={pl.info()['D']})",
               file=sys.stderr, flush=True)
@@ -202,21 +374,22 @@ def main():
         modes = {"propagation": (1,), "propagation_mfma": (2,), "propagation_small": (3, 4)}[dom]
         mode = modes[0]
         units = sum(pp for pp, md in zip(info["prop_pairs"], info["prop_mode"]) if md in modes)
-        flop = units * n_rhs * flops_per_eval(P)
+        fpu = FLOP_PROP * flop_scale(P)
         unit_txt = "(parent-cone node, relevant child) evaluations"
         bound = "mfma" if mode >= 2 else "alu"
     elif dom == "interpolation":
         units = sum(info["cousin_pairs"])
-        flop = units * n_rhs * flops_per_eval(P)
+        fpu = FLOP_INTERP * flop_scale(P)
         unit_txt = "(target, cousin box) evaluations"
     elif dom == "leaf":
         units = info["leaf_pairs"]
-        flop = units * n_rhs * 30
+        fpu = FLOP_LEAF
         unit_txt = "(leaf-cone node, source) evaluations"
     else:
         units = info["near_pairs"]
-        flop = units * n_rhs * 30
+        fpu = FLOP_NEAR
         unit_txt = "near-field pairs"
+    flop = units * n_rhs * fpu
     per_launch = flop / launches
     achieved = per_launch / (avg_ms * 1e-3) / 1e12
     peak = PEAK_BF16X3_PRODUCT if (head == "bf16x3" and dom == "propagation_small") \
@@ -228,7 +401,7 @@ def main():
                 "avg_launch_ms": round(avg_ms, 4),
                 "flop_per_launch": per_launch,
                 "units_per_step": units,
-                "flop_per_unit_per_rhs": flops_per_eval(P) if dom.startswith("prop") or dom == "interpolation" else 30,
+                "flop_per_unit_per_rhs": fpu,
                 "unit_desc": unit_txt}
 
     if batch:
@@ -270,7 +443,7 @@ def main():
         # targets, which is also the reference for the error estimate
         # (relative l2, eq. errorcomputation; max over RHS and instances).
         import oracle
-        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+        threads = oracle.threads()
         per_inst = args.samples_batch if batch else None
         t_cpu, pairs = 0.0, 0
         errs = {prec: 0.0 for prec in res}
@@ -298,6 +471,13 @@ def main():
         for other in ("fp64", "bf16x3"):
             if other in line:
                 line[other]["rel_err"] = errs[other]
+        line["cpu"] = cpu_info()
+        line["cpu_baseline"]["cores"] = line["cpu"]["omp_threads"]
+        if args.cpu_ifgf_n > 0:
+            line["cpu_baseline_ifgf"] = cpu_ifgf_leg(args.cpu_ifgf_n, args.steps, args.warmup)
+    if args.configs != "none":
+        names = None if args.configs == "all" else args.configs.split(",")
+        line["configs"] = run_configs(args.config_steps, 2, names)
     print(json.dumps(line), flush=True)
 
 

@@ -37,6 +37,8 @@ def _load():
         lib.oracle_interp_eval.argtypes = [c_int, c_int, P, P, c_i64, P]
         lib.oracle_cone_keys.argtypes = [P, c_i64, c_dbl, c_dbl, P, P, c_int, P, c_i64]
         lib.oracle_cone_keys.restype = c_i64
+        lib.oracle_threads.argtypes = []
+        lib.oracle_threads.restype = c_int
         for f in (lib.oracle_direct_sum, lib.oracle_ifgf,
                   lib.oracle_partition_counts, lib.oracle_interp_nodes,
                   lib.oracle_interp_eval):
@@ -107,7 +109,7 @@ def ifgf(points, dens, kappa, p_s=3, p_ang=5, leaf_size=0.25,
                            (1 if near else 0) | (2 if far else 0), grid_rule,
                            leaf_max, leaf_abs)
     out = np.zeros(2 * n, dtype=np.float64)
-    info = np.zeros(2 + 2 * 32, dtype=np.float64)
+    info = np.zeros(2 + 2 * 32 + 2, dtype=np.float64)
     rc = _load().oracle_ifgf(_ptr(p), n, _ptr(a), float(kappa),
                              float(leaf_size), _ptr(opts), _ptr(dopts), _ptr(out),
                              _ptr(info))
@@ -119,7 +121,13 @@ def ifgf(points, dens, kappa, p_s=3, p_ang=5, leaf_size=0.25,
     D = int(info[0])
     return res, {"D": D, "H1": float(info[1]),
                  "boxes": [int(info[2 * d]) for d in range(1, D + 1)],
-                 "cones": [int(info[2 * d + 1]) for d in range(1, D + 1)]}
+                 "cones": [int(info[2 * d + 1]) for d in range(1, D + 1)],
+                 "setup_s": float(info[66]), "eval_s": float(info[67])}
+
+
+def threads():
+    """OpenMP threads used by the oracle's parallel loops."""
+    return int(_load().oracle_threads())
 
 
 def partition_counts(points, kappa, leaf_size=0.25, levels=0, leaf_max=0.0,

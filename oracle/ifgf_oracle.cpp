@@ -48,8 +48,11 @@
 // error against the direct sum.  Its values at the default parameters are
 // otherwise "parity unpinned": the paper prints no worked example.
 
+#include <omp.h>
+
 #include <algorithm>
 #include <array>
+#include <chrono>
 #include <cmath>
 #include <complex>
 #include <cstdint>
@@ -154,6 +157,7 @@ struct Oracle {
   Options o{};
   int D = 0;
   double H1 = 0, corner[3] = {0, 0, 0};
+  double setup_seconds = 0, eval_seconds = 0;  // wall times of run()
   std::vector<int64_t> order;      // sorted position -> user index
   std::vector<double> X[3];        // sorted coordinates (SoA)
   std::vector<cplx> A;             // sorted densities
@@ -633,8 +637,11 @@ struct Oracle {
     t_a.resize(o.p_ang);
     for (int j = 0; j < o.p_s; ++j) t_s[j] = std::cos((2.0 * j + 1.0) * PI / (2.0 * o.p_s));
     for (int j = 0; j < o.p_ang; ++j) t_a[j] = std::cos((2.0 * j + 1.0) * PI / (2.0 * o.p_ang));
+    auto t0 = std::chrono::steady_clock::now();
     build_tree(leaf_size);
     build_cones();
+    auto t1 = std::chrono::steady_clock::now();
+    setup_seconds = std::chrono::duration<double>(t1 - t0).count();
     std::vector<cplx> out(n, cplx(0, 0));
     if (o.stages & 1) near_field(out);
     if (o.stages & 2) {
@@ -644,6 +651,7 @@ struct Oracle {
         if (d > 3 && o.mode == 0) propagation(d);
       }
     }
+    eval_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count();
     if (failed) return 3;
     for (int64_t i = 0; i < n; ++i) {
       out_user[2 * order[i]] = out[i].real();
@@ -655,8 +663,11 @@ struct Oracle {
 
 // opts: {p_s, p_ang, ns, nt, np, levels, mode, stages, grid_rule}
 // dopts: {leaf_max, leaf_abs} (may be null: both 0)
-// info (optional, length >= 2 + 2*32): [D, H1, then per level d=1..D the
-// number of relevant boxes and relevant cones].
+// info (optional, length >= 2 + 2*32 + 2): [D, H1, then per level d=1..D the
+// number of relevant boxes and relevant cones, then at [66] the wall time of
+// the set-up (tree, lists, relevant cones) and at [67] that of the
+// evaluation (near field, leaf evaluations, interpolation, propagation), in
+// seconds].
 // Options of the oracle from the flat arrays of the C interface; false when
 // they do not define a level rule (kappa = 0 needs levels or leaf_abs).
 static bool read_options(Options& o, const int* opts, const double* dopts,
@@ -692,9 +703,14 @@ extern "C" int oracle_ifgf(const double* pts, int64_t n, const double* dens,
       info[2 * d] = (double)O.lev[d].boxes.size();
       info[2 * d + 1] = (double)O.lev[d].cones.size();
     }
+    info[66] = O.setup_seconds;
+    info[67] = O.eval_seconds;
   }
   return rc;
 }
+
+// OpenMP threads the oracle's parallel loops use.
+extern "C" int oracle_threads() { return omp_get_max_threads(); }
 
 // Interaction count per target: points in U B^D(x) (self included) plus the
 // points of every cousin box at levels D..3.  The paper's partition of the

@@ -61,33 +61,30 @@ def test_full_size_vs_direct_sum(name, precision):
 
 def test_batch48_fp32_vs_direct_sum():
     """batch48 (48 instances, N from 4k to 200k, 4 RHS), planned as bench.py
-    plans it: per-instance accuracy control with leaves capped at 0.3
-    wavelengths (the rounding of the level rule alone leaves 0.31 to 0.35
-    wavelengths on ten instances, where the method's error at
-    (P_s, P_ang) = (3, 5) reaches 1.06e-4).  FP32-mixed agrees with an FP64
-    apply of the same batch to 2e-5 per instance and RHS, element by element
-    (its rounding), and with the FP64 direct sum to relative l2 <= 1e-4 on
-    every instance and RHS (eq. errorcomputation).  256 sampled targets per
-    instance."""
+    plans it (workloads.plan_options: leaf cone grid (3, 4, 8)).  FP32-mixed
+    agrees with an FP64 apply of the same batch to 2e-5 per instance and
+    RHS, element by element (its rounding), and with the FP64 direct sum to
+    relative l2 <= 1e-4 on every instance and RHS (eq. errorcomputation) over
+    the workload's error set: each instance's 4,096 sampled targets, or all
+    of its points when it has fewer."""
     import paper_2112_15198_amd as ifgf
     insts = W.make("batch48")
     pts = [x.points for x in insts]
     kap = [x.kappa for x in insts]
     dens = np.concatenate([x.dens for x in insts], axis=1)
-    say("batch48 fp32", len(insts), "instances", dens.shape[1], "points")
-    pl = ifgf.plan_batched(pts, kap, precision="fp32", n_rhs=4, leaf_grid=(2, 4, 8),
-                           autotune=True, leaf_max=W.BATCH_LEAF_MAX)
+    popts = W.plan_options("batch48")
+    say("batch48 fp32", len(insts), "instances", dens.shape[1], "points", popts)
+    pl = ifgf.plan_batched(pts, kap, precision="fp32", n_rhs=4, autotune=True, **popts)
     out32 = graph_apply(pl, dens, "fp32")
     pl.close()
     say("batch48 fp64")
-    pl = ifgf.plan_batched(pts, kap, precision="fp64", n_rhs=4, leaf_grid=(2, 4, 8),
-                           leaf_max=W.BATCH_LEAF_MAX)
+    pl = ifgf.plan_batched(pts, kap, precision="fp64", n_rhs=4, **popts)
     out64 = graph_apply(pl, dens, "fp64", graph=False)
     pl.close()
     off, worst = 0, 0.0
     for i, x in enumerate(insts):
         ni = x.points.shape[0]
-        tg = x.targets[:256]
+        tg = x.targets
         for r in range(4):
             g32 = out32[r, off:off + ni][tg]
             g64 = out64[r, off:off + ni][tg]
