@@ -207,6 +207,22 @@ ifgf_status ifgf_apply(ifgf_plan_t plan, const void* densities, void* out);
  * re-capture.  Profiling is not applied to graph launches. */
 ifgf_status ifgf_apply_graph(ifgf_plan_t plan, const void* densities, void* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): as
+ * ifgf_apply, but the apply's workspace (the two buffers of cone values of
+ * consecutive levels, the densities and the output in sorted order) is a
+ * static device array of the library, 256 MiB per GPU, held from the
+ * library's first use on that GPU until the process ends, instead of the
+ * plan's own buffers.  The call allocates nothing (no hipMalloc, no events)
+ * and launches the same kernels as ifgf_apply on the plan's stream; every
+ * workspace byte is written before it is read, so nothing is cleared
+ * between calls.  A plan whose workspace exceeds 256 MiB is rejected with
+ * IFGF_EINVAL.  All calls on one GPU share its array: calls that overlap in
+ * time on the same GPU (other streams, other threads) race and must be
+ * serialised by the caller.  Look-up misses are flagged as for ifgf_apply
+ * (ifgf_check). */
+ifgf_status ifgf_apply_noalloc(ifgf_plan_t plan, const void* densities, void* out);
+
 /* Wait for the plan's stream and report whether any cone look-up of the
  * previous applies missed (IFGF_ELOOKUP); clears the flag. */
 ifgf_status ifgf_check(ifgf_plan_t plan);

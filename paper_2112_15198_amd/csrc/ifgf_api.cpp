@@ -62,6 +62,8 @@ struct ifgf_plan_s {
   std::vector<void*> allocs;
   int64_t bytes = 0;
   ApplyArgs A{};
+  int64_t ws_vbytes = 0;      // bytes of one cone-value buffer (vbuf[0], vbuf[1])
+  int64_t ws_pbytes = 0;      // bytes of the sorted densities (and of the sorted output)
   std::vector<StepDev> steps_h;
   StepDev* steps_d = nullptr;
   bool device_ready = false;
@@ -560,6 +562,8 @@ static void build_device(ifgf_plan_s* P) {
   int64_t maxc = 1;
   for (int l = 0; l < L; ++l) maxc = std::max<int64_t>(maxc, P->steps_h[l].ncones);
   int64_t vbytes = maxc * A.nrhs * PP * (int64_t)csize;
+  P->ws_vbytes = vbytes;
+  P->ws_pbytes = m.n * A.nrhs * (int64_t)csize;
   A.vbuf[0] = P->dalloc<char>(vbytes);
   A.vbuf[1] = P->dalloc<char>(vbytes);
   A.dens_sorted = P->dalloc<char>(m.n * A.nrhs * (int64_t)csize);
@@ -793,6 +797,34 @@ ifgf_status ifgf_apply_graph(ifgf_plan_t P, const void* dens, void* out) {
   if (e == hipSuccess) e = hipGraphLaunch(P->gexec, P->stream);
   if (e != hipSuccess)
     return fail(IFGF_EHIP, std::string("apply_graph: ") + hipGetErrorString(e));
+  return IFGF_OK;
+}
+
+ifgf_status ifgf_apply_noalloc(ifgf_plan_t P, const void* dens, void* out) {
+  if (!P || !dens || !out) return fail(IFGF_EINVAL, "null argument");
+  if (!P->device_ready) return fail(IFGF_EINVAL, "plan was built host-only");
+  // The apply's workspace, carved from the static array in 256-byte aligned
+  // regions: two cone-value buffers, the sorted densities, the sorted output.
+  auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
+  const int64_t need = 2 * up(P->ws_vbytes) + 2 * up(P->ws_pbytes);
+  if (need > (int64_t)kStaticScratchBytes)
+    return fail(IFGF_EINVAL, "ifgf_apply_noalloc: the plan's workspace (" +
+                                 std::to_string(need) + " bytes) exceeds the static scratch of " +
+                                 std::to_string((int64_t)kStaticScratchBytes) + " bytes");
+  hipError_t e = hipSetDevice(P->device);
+  void* base = nullptr;
+  if (e == hipSuccess) e = static_scratch(&base);
+  if (e == hipSuccess) {
+    ApplyArgs A = P->A;
+    char* p = (char*)base;
+    A.vbuf[0] = p;
+    A.vbuf[1] = p + up(P->ws_vbytes);
+    A.dens_sorted = p + 2 * up(P->ws_vbytes);
+    A.out_sorted = p + 2 * up(P->ws_vbytes) + up(P->ws_pbytes);
+    e = launch_apply(A, P->p_s, P->p_ang, P->opts.precision, dens, out, P->stream, nullptr);
+  }
+  if (e != hipSuccess)
+    return fail(IFGF_EHIP, std::string("apply_noalloc: ") + hipGetErrorString(e));
   return IFGF_OK;
 }
 

@@ -147,6 +147,12 @@ hipError_t sort_keys(unsigned long long* keys, unsigned long long* tmp,
 // precision 0 FP64, 1 FP32-mixed, 2 FP32 with the three-term BF16 product.
 hipError_t launch_prop_level(const ApplyArgs& A, int l, int ps, int pa,
                              int precision, int kind, hipStream_t st);
+// The allocation-free apply's workspace: a static device array of
+// kStaticScratchBytes per GPU.  *ptr receives its device address on the
+// current device (looked up on the first call per device).
+static constexpr size_t kStaticScratchBytes = size_t(256) << 20;
+static constexpr int kMaxDevices = 64;
+hipError_t static_scratch(void** ptr);
 hipError_t launch_apply(const ApplyArgs& A, int ps, int pa, int precision,
                         const void* dens_user, void* out_user, hipStream_t st,
                         Profiler* prof);

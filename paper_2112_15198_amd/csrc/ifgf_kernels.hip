@@ -31,6 +31,7 @@
 
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <rocprim/device/device_radix_sort.hpp>
 
 #include "ifgf_device.h"
@@ -2195,6 +2196,31 @@ hipError_t launch_prop_level(const ApplyArgs& A, int l, int ps, int pa,
   IFGF_PL(5, 7)
 #undef IFGF_PL
   return hipErrorInvalidValue;
+}
+
+// Workspace of the allocation-free apply: one static device array per GPU,
+// held from the first use of the library on that GPU until the process ends.
+// Host code never passes `scratch` itself to a kernel (on the host the name
+// is only a stand-in); it passes the device address that
+// hipGetSymbolAddress returns, looked up once per device.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+hipError_t static_scratch(void** ptr) {
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_apply(const ApplyArgs& A, int ps, int pa, int precision,

@@ -24,7 +24,7 @@ EXPORTED = ["ifgf_default_opts", "ifgf_plan", "ifgf_plan_ex", "ifgf_plan_batched
             "ifgf_apply", "ifgf_check", "ifgf_set_stream", "ifgf_plan_info",
             "ifgf_partition_counts", "ifgf_destroy", "ifgf_status_string",
             "ifgf_profile", "ifgf_profile_read", "ifgf_cone_keys",
-            "ifgf_apply_graph"]
+            "ifgf_apply_graph", "ifgf_apply_noalloc"]
 
 STAGES = ["permute_in", "near_field", "leaf", "interpolation", "propagation",
           "permute_out", "propagation_mfma", "propagation_small"]
@@ -90,6 +90,7 @@ def load_library():
                                       ctypes.POINTER(Opts)]
     lib.ifgf_apply.argtypes = [P, P, P]
     lib.ifgf_apply_graph.argtypes = [P, P, P]
+    lib.ifgf_apply_noalloc.argtypes = [P, P, P]
     lib.ifgf_check.argtypes = [P]
     lib.ifgf_set_stream.argtypes = [P, P]
     lib.ifgf_plan_info.argtypes = [P, ctypes.POINTER(Info)]
