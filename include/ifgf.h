@@ -124,6 +124,12 @@ typedef struct ifgf_opts {
                        of the file takes the kernels recorded there instead
                        of timing them, and a plan that times them appends a
                        line. */
+  int prop_tables;  /* plan-time tables of the matrix-core propagation (the
+                       node geometry of every parent cone index and child
+                       octant, which does not depend on the box): 0 builds
+                       them for the steps nearest the leaves within the bytes
+                       of one cone-value buffer (at least 1 GiB), 1 never,
+                       2 for every step.  Results are identical either way. */
 } ifgf_opts;
 
 /* Size information about a plan (ifgf_plan_info). */
@@ -156,6 +162,7 @@ typedef struct ifgf_info {
   double plan_seconds;    /* wall time of plan construction */
   int tune_cache_hit;     /* 1 when the kernels came from the tuning cache */
   int grid_doubling;      /* 1 when the cone grid doubles per level up */
+  int64_t prop_table_bytes; /* device bytes of the propagation tables */
 } ifgf_info;
 
 /* Fill *opts with the defaults: FP64, 1 RHS, leaf grid {2,4,8}, automatic

@@ -130,6 +130,7 @@ static ifgf_status validate(int p_s, int p_ang, const ifgf_opts& o) {
   if (!(o.cone_margin >= 0.0 && o.cone_margin < 0.25))
     return fail(IFGF_EINVAL, "cone_margin must be in [0, 0.25)");
   if (o.grid_rule < 0 || o.grid_rule > 2) return fail(IFGF_EINVAL, "grid_rule must be 0, 1 or 2");
+  if (o.prop_tables < 0 || o.prop_tables > 2) return fail(IFGF_EINVAL, "prop_tables must be 0, 1 or 2");
   bool ok = (p_s == 3 && p_ang == 5) || (p_s == 2 && p_ang == 3) || (p_s == 5 && p_ang == 7);
   if (!ok && !o.host_only)
     return fail(IFGF_EUNSUPPORTED, "no kernel compiled for this (p_s, p_ang)");
@@ -313,6 +314,35 @@ static void autotune(ifgf_plan_s* P) {
                     hipMemcpyHostToDevice));
 }
 
+// Plan-time tables of the matrix-core propagation: the box-independent
+// record (node geometry seen from each child octant, grouping of the nodes
+// by child cone) of every (instance, gamma') group of a step, so that the
+// apply reads it instead of recomputing it for every chunk of boxes.
+// Steps are taken from the leaf upwards (where groups hold the most boxes)
+// while the tables stay within the budget: the bytes of one cone-value
+// buffer (at least 1 GiB) with prop_tables = 0, none with 1, all with 2.
+static void build_prop_tables(ifgf_plan_s* P, int64_t vbytes) {
+  ApplyArgs& A = P->A;
+  const int rec = prop_table_record_bytes(P->p_s, P->p_ang, P->opts.precision);
+  if (rec <= 0 || P->opts.prop_tables == 1) return;
+  const int64_t budget = P->opts.prop_tables == 2 ? INT64_MAX
+                                                   : std::max<int64_t>(vbytes, int64_t(1) << 30);
+  int64_t used = 0;
+  for (int l = 1; l < A.n_steps; ++l) {
+    StepDev& Q = P->steps_h[l];
+    if (Q.ngroups <= 0 || Q.ncones <= 0) continue;
+    const int64_t bytes = Q.ngroups * 8 * (int64_t)rec;
+    if (used + bytes > budget) break;
+    Q.prop_table = P->dalloc<unsigned char>(bytes);
+    used += bytes;
+    HIP_TRY(hipMemcpy(P->steps_d, P->steps_h.data(), sizeof(StepDev) * A.n_steps,
+                      hipMemcpyHostToDevice));
+    HIP_TRY(launch_prop_table(A, l - 1, P->p_s, P->p_ang, P->opts.precision, Q.ngroups,
+                              P->stream));
+  }
+  P->info.prop_table_bytes = used;
+}
+
 static void build_device(ifgf_plan_s* P) {
   Merged& m = P->m;
   const int ps = P->p_s, pa = P->p_ang, PP = ps * pa * pa;
@@ -469,6 +499,8 @@ static void build_device(ifgf_plan_s* P) {
       D.nchunks = 0;
       D.nschunks = 0;
       D.nmchunks = 0;
+      D.ngroups = 0;
+      D.prop_table = nullptr;
       if (l >= 1 && count > 0) {
         const uint64_t ng = (uint64_t)D.ngrid;
         std::vector<int32_t> order(count);
@@ -486,12 +518,15 @@ static void build_device(ifgf_plan_s* P) {
         const int cbox = chunk_boxes(P->opts.precision, P->opts.n_rhs);
         const int sbox = small_chunk_boxes(P->opts.n_rhs, 1);
         const int mbox = small_chunk_boxes(P->opts.n_rhs, kMediumWaves);
-        std::vector<int64_t> cstart, sstart, mstart;
-        std::vector<int32_t> clen, slen, mlen;
+        std::vector<int64_t> cstart, sstart, mstart, gfirst;
+        std::vector<int32_t> clen, slen, mlen, sgroup, mgroup;
         int64_t groups = 0;
         for (int64_t i = 0; i < (int64_t)count; ++i) {
           bool same = i > 0 && gk(order[i]) == gk(order[i - 1]);
-          if (!same) ++groups;
+          if (!same) {
+            ++groups;
+            gfirst.push_back(i);
+          }
           if (!same || clen.back() == cbox) {
             cstart.push_back(i);
             clen.push_back(0);
@@ -500,11 +535,13 @@ static void build_device(ifgf_plan_s* P) {
           if (!same || slen.back() == sbox) {
             sstart.push_back(i);
             slen.push_back(0);
+            sgroup.push_back((int32_t)(groups - 1));
           }
           slen.back() += 1;
           if (!same || mlen.back() == mbox) {
             mstart.push_back(i);
             mlen.push_back(0);
+            mgroup.push_back((int32_t)(groups - 1));
           }
           mlen.back() += 1;
         }
@@ -533,6 +570,10 @@ static void build_device(ifgf_plan_s* P) {
           D.mchunk_start = P->upload(mstart);
           D.mchunk_len = P->upload(mlen);
           D.nmchunks = (int64_t)mstart.size();
+          D.ngroups = groups;
+          D.group_first = P->upload(gfirst);
+          D.schunk_group = P->upload(sgroup);
+          D.mchunk_group = P->upload(mgroup);
         }
       }
       int64_t pairs_l = 0;
@@ -568,6 +609,7 @@ static void build_device(ifgf_plan_s* P) {
   A.vbuf[1] = P->dalloc<char>(vbytes);
   A.dens_sorted = P->dalloc<char>(m.n * A.nrhs * (int64_t)csize);
   A.out_sorted = P->dalloc<char>(m.n * A.nrhs * (int64_t)csize);
+  build_prop_tables(P, vbytes);
   HIP_TRY(hipStreamSynchronize(st));
   if (P->opts.autotune) autotune(P);
   P->device_ready = true;

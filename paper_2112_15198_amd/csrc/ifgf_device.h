@@ -60,6 +60,14 @@ struct StepDev {
   int64_t nmchunks;           // ... and of small_chunk_boxes(nrhs, kMediumWaves)
   const int64_t* mchunk_start;
   const int* mchunk_len;
+  // Groups: the runs of gslot sharing (instance, gamma).  The plan-time
+  // table holds the box-independent record of every (group, octant)
+  // (prop_table_record_bytes each, group-major), or is null.
+  int64_t ngroups;
+  const int64_t* group_first; // first index into gslot of each group
+  const int* schunk_group;    // group of each one-wave chunk
+  const int* mchunk_group;    // group of each kMediumWaves-wave chunk
+  unsigned char* prop_table;
 };
 
 // Propagation kernels of a level: per node, matrix-core blocks, one-wave
@@ -142,6 +150,11 @@ hipError_t launch_build_lookup(const unsigned long long* keys, int64_t n,
 hipError_t sort_keys(unsigned long long* keys, unsigned long long* tmp,
                      int64_t n, int end_bit, void* scratch,
                      size_t* scratch_bytes, hipStream_t st);
+// Bytes of one (group, octant) record of a propagation table.
+int prop_table_record_bytes(int ps, int pa, int precision);
+// Fill the propagation table of step l + 1 (every group, every octant).
+hipError_t launch_prop_table(const ApplyArgs& A, int l, int ps, int pa, int precision,
+                             int64_t ngroups, hipStream_t st);
 // One Propagation launch (step l -> l + 1) with kernel `kind` (kPropNode,
 // kPropGrouped, kPropSmall, kPropMedium), for timing at plan time;
 // precision 0 FP64, 1 FP32-mixed, 2 FP32 with the three-term BF16 product.

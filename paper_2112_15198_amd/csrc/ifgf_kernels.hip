@@ -1420,6 +1420,36 @@ __device__ __forceinline__ void small_load_b(const typename C2<T>::type* __restr
   }
 }
 
+// B values of one lane as in small_load_b, one part of each complex value:
+// real parts for part 0, imaginary parts for part 1.
+template <int PS, int PA, typename T, int MAXR>
+__device__ __forceinline__ void small_load_b1(const typename C2<T>::type* __restrict__ vp, int kq,
+                                              int part, T* b) {
+  typedef SmallProp<PS, PA, T, MAXR> SP;
+  typedef typename C2<T>::type CT;
+#pragma unroll
+  for (int g = 0; g < SP::NG; ++g) {
+    const int q0 = SP::slot_row(g, kq);
+    const CT* src = vp + (q0 >= 0 ? q0 : 0);  // zero slot: weight 0
+    if constexpr (sizeof(T) == 4) {
+      typedef T v4u __attribute__((ext_vector_type(4), aligned(8)));
+#pragma unroll
+      for (int c = 0; c + 1 < PA; c += 2) {
+        const v4u x = *reinterpret_cast<const v4u*>(src + c);
+        b[g * PA + c] = part ? x.y : x.x;
+        b[g * PA + c + 1] = part ? x.w : x.z;
+      }
+      if constexpr (PA & 1) {
+        const CT x = src[PA - 1];
+        b[g * PA + PA - 1] = part ? x.y : x.x;
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < PA; ++c) b[g * PA + c] = reinterpret_cast<const T*>(src + c)[part];
+    }
+  }
+}
+
 // Three-term BF16 form of the propagation product (an addition beyond the
 // paper): each FP32 operand x is split into x_hi = bf16(x) and
 // x_lo = bf16(x - x_hi) (round to nearest even), and A B is taken as
@@ -1458,12 +1488,13 @@ __device__ __forceinline__ void split_b(const float* br, const float* bi, SplitB
 // instead of read from s_L (grouped order); wak, wbk are the weights of
 // L_a(kq), L_b(kq).  SPLIT: the product in three-term BF16 form, B taken
 // from sb.
-template <int PS, int PA, typename T, int MAXR, bool LREG, bool SPLIT>
+template <int PS, int PA, typename T, int MAXR, bool LREG, bool SPLIT, bool CPLX>
 __device__ __forceinline__ void small_tile(const T* s_L, const T* s_u, const ChebConst& cheb,
                                            T wak, T wbk, const typename C2<T>::type* s_ratp,
                                            const unsigned char* s_rows,
                                            typename C2<T>::type* y, int rb, int rlen, int yb,
-                                           bool colok, int lane, const T* br, const T* bi,
+                                           bool colok, int lane, int part, const T* br,
+                                           const T* bi,
                                            const SplitB<SmallProp<PS, PA, T, MAXR>::NK>& sb) {
   typedef SmallProp<PS, PA, T, MAXR> SP;
   typedef typename C2<T>::type CT;
@@ -1501,6 +1532,51 @@ __device__ __forceinline__ void small_tile(const T* s_L, const T* s_u, const Che
     const int mm = Mfma<T>::row(lane, r4);
     pe[r4] = mm < rlen ? (int)s_rows[rb + mm] : -1;
     rat[r4] = s_ratp[pe[r4] >= 0 ? pe[r4] : 0];
+  }
+  if constexpr (CPLX) {
+    // Columns are (child, rhs, part): the lane's B values are the real
+    // (part 0) or imaginary (part 1) parts, and its partner lane (col ^ 1)
+    // holds the other part of the same complex column.
+    V4 acc = {0, 0, 0, 0};
+    if constexpr (SPLIT) {
+      static_assert(sizeof(T) == 4, "three-term BF16 form of the FP32 product");
+      constexpr int NK = SP::NK;
+#pragma unroll
+      for (int st = 0; st < SplitB<NK>::NS; ++st) {
+        bf8v ah, al;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int v = 8 * st + i;
+          const float x = v < NK ? ab[v < NK ? v / PA : 0] * Lc[v < NK ? v % PA : 0] : 0.f;
+          const __bf16 h = (__bf16)x;
+          ah[i] = h;
+          al[i] = (__bf16)(x - (float)h);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, sb.rh[st], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, sb.rl[st], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, sb.rh[st], acc, 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int g = 0; g < NG; ++g)
+#pragma unroll
+        for (int c = 0; c < PA; ++c) acc = Mfma<T>::mma(ab[g] * Lc[c], br[g * PA + c], acc);
+    }
+    T oth[4];
+#pragma unroll
+    for (int r4 = 0; r4 < 4; ++r4) oth[r4] = __shfl_xor(acc[r4], 1);
+    if (colok) {
+      T* yf = reinterpret_cast<T*>(y);
+#pragma unroll
+      for (int r4 = 0; r4 < 4; ++r4) {
+        if (pe[r4] >= 0) {
+          const T re = part ? oth[r4] : acc[r4], im = part ? acc[r4] : oth[r4];
+          const T v = part ? re * rat[r4].y + im * rat[r4].x : re * rat[r4].x - im * rat[r4].y;
+          yf[2 * (yb + pe[r4]) + part] += v;
+        }
+      }
+    }
+    return;
   }
   V4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
   if constexpr (SPLIT) {
@@ -1551,6 +1627,155 @@ __device__ __forceinline__ void small_tile(const T* s_L, const T* s_u, const Che
   }
 }
 
+// Box-independent data of one (parent cone index gamma', octant o) of a
+// propagation step, in one record (the same layout in LDS and in the
+// plan-time table): the number of distinct child cones na and of M-tiles
+// nm; the distinct child cones; the nodes grouped by child cone (rows:
+// node at grouped position, rbeg: first position of each child cone); the
+// M-tiles (child cone, first position); the local coordinates u of every
+// node in its child cone; the ratio G(x, x_k)/G(x, x_j) of every node.
+template <int P, typename T>
+struct OctRec {
+  typedef typename C2<T>::type CT;
+  static constexpr int kNa = 0, kNm = 4;
+  static constexpr int kDist = 16;                                  // int[P]
+  static constexpr int kRows = kDist + 4 * P;                       // uchar[P]
+  static constexpr int kRbeg = kRows + P;                           // uchar[P + 1]
+  static constexpr int kMk = kRbeg + P + 1;                         // uchar[P]
+  static constexpr int kMr = kMk + P;                               // uchar[P]
+  static constexpr int kU = (kMr + P + 15) / 16 * 16;               // T[3 P]
+  static constexpr int kRat = (kU + 3 * P * (int)sizeof(T) + 15) / 16 * 16;  // CT[P]
+  static constexpr int kSize = (kRat + P * (int)sizeof(CT) + 15) / 16 * 16;
+  unsigned char* b;
+  __device__ int& na() const { return *reinterpret_cast<int*>(b + kNa); }
+  __device__ int& nm() const { return *reinterpret_cast<int*>(b + kNm); }
+  __device__ int* dist() const { return reinterpret_cast<int*>(b + kDist); }
+  __device__ unsigned char* rows() const { return b + kRows; }
+  __device__ unsigned char* rbeg() const { return b + kRbeg; }
+  __device__ unsigned char* mk() const { return b + kMk; }
+  __device__ unsigned char* mr() const { return b + kMr; }
+  __device__ T* u() const { return reinterpret_cast<T*>(b + kU); }
+  __device__ CT* ratp() const { return reinterpret_cast<CT*>(b + kRat); }
+};
+
+// Node geometry of parent cone index (is, it, ip) of step l + 1 seen from
+// the child in octant o, for nodes p = t0, t0 + stride, ...: the child cone
+// alpha(p), the local coordinates u(p) and the ratio G(x_p, x_k)/G(x_p, x_j)
+// (phase reduced in FP64).
+template <int PS, int PA, typename T>
+__device__ __forceinline__ void octant_geometry(const StepDev& S, const StepDev& Q, double hp,
+                                                double hc, double Hc, double kappa, int is,
+                                                int it, int ip, int o, int t0, int stride,
+                                                int* s_alpha, OctRec<PS * PA * PA, T> R) {
+  typedef typename C2<T>::type CT;
+  constexpr int P = PS * PA * PA;
+  for (int p = t0; p < P; p += stride) {
+    const int a = p / (PA * PA), bb = (p / PA) % PA, cc = p % PA;
+    double yp[3];
+    node_offset<PS, PA>(Q, hp, is, it, ip, a, bb, cc, yp);
+    double y0, y1, y2, rj;
+    {
+      IFGF_NO_CONTRACT
+      y0 = yp[0] - (((o >> 2) & 1) ? 0.5 * Hc : -0.5 * Hc);
+      y1 = yp[1] - (((o >> 1) & 1) ? 0.5 * Hc : -0.5 * Hc);
+      y2 = yp[2] - ((o & 1) ? 0.5 * Hc : -0.5 * Hc);
+      rj = sqrt(yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]);
+    }
+    ConeCoord cr = cone_coord(S, hc, y0, y1, y2);
+    double u0, u1, u2;
+    const int cs = cone_index(cr.q[0], S.ns, u0);
+    const int ct = cone_index(cr.q[1], S.nt, u1);
+    const int cp = cone_index(cr.q[2], S.np, u2);
+    s_alpha[p] = (cs * S.nt + ct) * S.np + cp;
+    T* u = R.u();
+    u[3 * p] = (T)u0;
+    u[3 * p + 1] = (T)u1;
+    u[3 * p + 2] = (T)u2;
+    T gcv, gsv;
+    expi<T>(kappa * (cr.r - rj), gcv, gsv);
+    const T amp = (T)(rj / cr.r);
+    R.ratp()[p] = CT{gcv * amp, gsv * amp};
+  }
+}
+
+// Distinct child cones, the nodes grouped by child cone and the M-tiles of
+// every child cone, from alpha(p) (one wave, ballots; lane holds nodes lane
+// and lane + 64).
+template <int P, typename T>
+__device__ __forceinline__ void octant_grouping(const int* s_alpha, int lane,
+                                                OctRec<P, T> R) {
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  const bool has0 = lane < P, has1 = lane + 64 < P;
+  const int a0 = has0 ? s_alpha[lane] : -1;
+  const int a1 = has1 ? s_alpha[lane + 64] : -1;
+  bool f0 = has0, f1 = has1;
+  int k0 = 0, k1 = 0, na = 0;
+  int* dist = R.dist();
+  for (;;) {
+    const unsigned long long m0 = __ballot(f0), m1 = __ballot(f1);
+    if (m0 == 0ull && m1 == 0ull) break;
+    const int lead = m0 ? __shfl(a0, __ffsll((long long)m0) - 1)
+                        : __shfl(a1, __ffsll((long long)m1) - 1);
+    if (f0 && a0 == lead) { k0 = na; f0 = false; }
+    if (f1 && a1 == lead) { k1 = na; f1 = false; }
+    if (lane == 0) dist[na] = lead;
+    ++na;
+  }
+  unsigned char* rows = R.rows();
+  int base = 0, nm = 0;
+  for (int k = 0; k < na; ++k) {
+    const unsigned long long m0 = __ballot(has0 && k0 == k), m1 = __ballot(has1 && k1 == k);
+    if (has0 && k0 == k) rows[base + __popcll(m0 & lt)] = (unsigned char)lane;
+    if (has1 && k1 == k) rows[base + __popcll(m0) + __popcll(m1 & lt)] = (unsigned char)(lane + 64);
+    const int rlen = __popcll(m0) + __popcll(m1);
+    const int ntk = (rlen + 15) >> 4;
+    if (lane < ntk) {
+      R.mk()[nm + lane] = (unsigned char)k;
+      R.mr()[nm + lane] = (unsigned char)(base + 16 * lane);
+    }
+    if (lane == 0) R.rbeg()[k] = base;
+    base += rlen;
+    nm += ntk;
+  }
+  if (lane == 0) {
+    R.rbeg()[na] = base;
+    R.na() = na;
+    R.nm() = nm;
+  }
+}
+
+// Plan-time table of a propagation step: one record per (group, octant),
+// a group being the relevant parent cones sharing (instance, gamma').  One
+// wave per record.
+template <int PS, int PA, typename T>
+__global__ void __launch_bounds__(64) prop_table_kernel(ApplyArgs A, int l) {
+  typedef OctRec<PS * PA * PA, T> R;
+  constexpr int P = PS * PA * PA;
+  __shared__ __align__(16) unsigned char s_rec[R::kSize];
+  __shared__ int s_alpha[P];
+  const StepDev& S = A.step[l];
+  const StepDev& Q = A.step[l + 1];
+  const int64_t gi = blockIdx.x >> 3;
+  const int o = blockIdx.x & 7;
+  const int lane = threadIdx.x;
+  const unsigned long long key0 = Q.cone_key[Q.gslot[Q.group_first[gi]]];
+  const int64_t j0 = (int64_t)(key0 / (unsigned long long)Q.ngrid);
+  const int64_t g = (int64_t)(key0 - (unsigned long long)j0 * Q.ngrid);
+  const int is = (int)(g / ((int64_t)Q.nt * Q.np));
+  const int it = (int)((g / Q.np) % Q.nt);
+  const int ip = (int)(g % Q.np);
+  const int inst = Q.inst[j0];
+  R rec{s_rec};
+  octant_geometry<PS, PA, T>(S, Q, Q.inst_h[inst], S.inst_h[inst], S.inst_H[inst],
+                             A.inst_kappa[inst], is, it, ip, o, lane, 64, s_alpha, rec);
+  __syncthreads();
+  octant_grouping<P, T>(s_alpha, lane, rec);
+  __syncthreads();
+  const uint4* src = reinterpret_cast<const uint4*>(s_rec);
+  uint4* dst = reinterpret_cast<uint4*>(Q.prop_table + (int64_t)blockIdx.x * R::kSize);
+  for (int i = lane; i < R::kSize / 16; i += 64) dst[i] = src[i];
+}
+
 // The children of the block's boxes are compacted per octant across the
 // whole block, so an N-tile holds 16 (child, rhs) columns of any of its
 // waves' boxes; the octant's work items (N-tile, M-tile) are cut into NWV
@@ -1566,19 +1791,27 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
   constexpr int P = SP::P, NAMAX = SP::NAMAX, LW = SP::LW;
   constexpr int NB = NWV * SP::WB;          // boxes per block
   constexpr bool LREG = NWV == 1;           // factors in registers (one wave)
+  // One wave: (child, rhs, part) columns, 8 complex columns per N-tile (its
+  // chunks hold few children per octant); several waves: (child, rhs)
+  // columns with the real and imaginary parts in separate products.
+  constexpr bool CPLX = NWV == 1;
   static_assert(P <= 128, "two nodes per lane");
   static_assert(NB <= 64, "one lane per box");
-  // Shared per octant.
+  typedef OctRec<P, T> Rec;
+  // Shared per octant: the octant's record (computed, or copied from the
+  // step's plan-time table), the child cone of every node while it is being
+  // computed, and the factors in grouped order.
   __shared__ __align__(16) T s_L[LREG ? 1 : P * LW];  // factors at grouped position pos
-  __shared__ T s_u[P * 3];                  // local coordinates of node p
-  __shared__ CT s_ratp[P];                  // ratio of node p
+  __shared__ __align__(16) unsigned char s_rec[Rec::kSize];
   __shared__ int s_alpha[P];                // child cone of node p
-  __shared__ unsigned char s_rows[P];       // node p at pos
-  __shared__ unsigned char s_rbeg[P + 1];   // first pos of each child cone
-  __shared__ int s_dist[P];                 // distinct child cones
-  __shared__ unsigned char s_mk[NWV > 1 ? P : 1];  // M-tile j: child cone, first pos
-  __shared__ unsigned char s_mr[NWV > 1 ? P : 1];
-  __shared__ int s_na, s_nm;
+  const Rec rec{s_rec};
+  const T* const s_u = rec.u();             // local coordinates of node p
+  const CT* const s_ratp = rec.ratp();      // ratio of node p
+  const unsigned char* const s_rows = rec.rows();  // node p at pos
+  const unsigned char* const s_rbeg = rec.rbeg();  // first pos of each child cone
+  const int* const s_dist = rec.dist();     // distinct child cones
+  const unsigned char* const s_mk = rec.mk();  // M-tile j: child cone, first pos
+  const unsigned char* const s_mr = rec.mr();
   // Per block.
   __shared__ CT s_y[NB * MAXR * P];
   __shared__ int s_slot[NB];
@@ -1595,6 +1828,12 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
   const int* clen = NWV == 1 ? Q.schunk_len : Q.mchunk_len;
   const int64_t g0 = cstart[blockIdx.x];
   const int nb = clen[blockIdx.x];          // boxes of this chunk, <= NB
+  // The step's table of octant records, and this chunk's group in it.
+  const unsigned char* const table =
+      Q.prop_table ? Q.prop_table +
+                         (int64_t)(NWV == 1 ? Q.schunk_group : Q.mchunk_group)[blockIdx.x] * 8 *
+                             Rec::kSize
+                   : nullptr;
   const unsigned long long key0 = Q.cone_key[Q.gslot[g0]];
   const int64_t j0 = (int64_t)(key0 / (unsigned long long)Q.ngrid);
   const int64_t g = (int64_t)(key0 - (unsigned long long)j0 * Q.ngrid);
@@ -1641,76 +1880,20 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
   for (int o = 0; o < 8; ++o) {
     const int no = s_no[o];
     if (no == 0) continue;  // uniform across the block
-    // Node geometry of octant o.
-    for (int p = tid; p < P; p += 64 * NWV) {
-      const int a = p / (PA * PA), bb = (p / PA) % PA, cc = p % PA;
-      double yp[3];
-      node_offset<PS, PA>(Q, hp, is, it, ip, a, bb, cc, yp);
-      double y0, y1, y2, rj;
-      {
-        IFGF_NO_CONTRACT
-        y0 = yp[0] - (((o >> 2) & 1) ? 0.5 * Hc : -0.5 * Hc);
-        y1 = yp[1] - (((o >> 1) & 1) ? 0.5 * Hc : -0.5 * Hc);
-        y2 = yp[2] - ((o & 1) ? 0.5 * Hc : -0.5 * Hc);
-        rj = sqrt(yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]);
-      }
-      ConeCoord cr = cone_coord(S, hc, y0, y1, y2);
-      double u0, u1, u2;
-      const int cs = cone_index(cr.q[0], S.ns, u0);
-      const int ct = cone_index(cr.q[1], S.nt, u1);
-      const int cp = cone_index(cr.q[2], S.np, u2);
-      s_alpha[p] = (cs * S.nt + ct) * S.np + cp;
-      s_u[3 * p] = (T)u0;
-      s_u[3 * p + 1] = (T)u1;
-      s_u[3 * p + 2] = (T)u2;
-      T gcv, gsv;
-      expi<T>(kappa * (cr.r - rj), gcv, gsv);
-      const T amp = (T)(rj / cr.r);
-      s_ratp[p] = CT{gcv * amp, gsv * amp};
+    if (table) {
+      // The octant's record from the plan-time table.
+      const uint4* src = reinterpret_cast<const uint4*>(table + o * Rec::kSize);
+      uint4* dst = reinterpret_cast<uint4*>(s_rec);
+      for (int i = tid; i < Rec::kSize / 16; i += 64 * NWV) dst[i] = src[i];
+      __syncthreads();
+    } else {
+      octant_geometry<PS, PA, T>(S, Q, hp, hc, Hc, kappa, is, it, ip, o, tid, 64 * NWV, s_alpha,
+                                 rec);
+      __syncthreads();
+      if (wave == 0) octant_grouping<P, T>(s_alpha, lane, rec);
+      __syncthreads();
     }
-    __syncthreads();
-    // Distinct child cones, the nodes grouped by child cone and the M-tiles
-    // of every child cone (wave 0, ballots; lane holds nodes lane and
-    // lane + 64).
-    if (wave == 0) {
-      const bool has0 = lane < P, has1 = lane + 64 < P;
-      const int a0 = has0 ? s_alpha[lane] : -1;
-      const int a1 = has1 ? s_alpha[lane + 64] : -1;
-      bool f0 = has0, f1 = has1;
-      int k0 = 0, k1 = 0, na = 0;
-      for (;;) {
-        const unsigned long long m0 = __ballot(f0), m1 = __ballot(f1);
-        if (m0 == 0ull && m1 == 0ull) break;
-        const int lead = m0 ? __shfl(a0, __ffsll((long long)m0) - 1)
-                            : __shfl(a1, __ffsll((long long)m1) - 1);
-        if (f0 && a0 == lead) { k0 = na; f0 = false; }
-        if (f1 && a1 == lead) { k1 = na; f1 = false; }
-        if (lane == 0) s_dist[na] = lead;
-        ++na;
-      }
-      int base = 0, nm = 0;
-      for (int k = 0; k < na; ++k) {
-        const unsigned long long m0 = __ballot(has0 && k0 == k), m1 = __ballot(has1 && k1 == k);
-        if (has0 && k0 == k) s_rows[base + __popcll(m0 & lt)] = (unsigned char)lane;
-        if (has1 && k1 == k) s_rows[base + __popcll(m0) + __popcll(m1 & lt)] = (unsigned char)(lane + 64);
-        const int rlen = __popcll(m0) + __popcll(m1);
-        const int ntk = (rlen + 15) >> 4;
-        if (NWV > 1 && lane < ntk) {  // one wave: its range starts at M-tile 0
-          s_mk[nm + lane] = (unsigned char)k;
-          s_mr[nm + lane] = (unsigned char)(base + 16 * lane);
-        }
-        if (lane == 0) s_rbeg[k] = base;
-        base += rlen;
-        nm += ntk;
-      }
-      if (lane == 0) {
-        s_rbeg[na] = base;
-        s_na = na;
-        s_nm = nm;
-      }
-    }
-    __syncthreads();
-    const int na = s_na, nm = s_nm;
+    const int na = rec.na(), nm = rec.nm();
     // Factors in grouped order (several waves); child cone slots of the
     // block's children.
     if constexpr (!LREG) {
@@ -1746,8 +1929,8 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
     // Work items (N-tile nt, M-tile j), nt major; wave w takes a contiguous
     // range and walks it unit by unit, a unit being the M-tiles of one
     // (nt, child cone k) in the range, with one B load per unit.
-    const int ncols = no * nrhs;
-    const int nit = ((ncols + 15) >> 4) * nm;
+    const int ncols = no * nrhs;  // complex columns (child, rhs)
+    const int nit = (CPLX ? (ncols + 7) >> 3 : (ncols + 15) >> 4) * nm;
     const int i0 = (int)(((int64_t)nit * wave) / NWV), i1 = (int)(((int64_t)nit * (wave + 1)) / NWV);
     int nt = i0 / nm, k = 0, rb = 0, rend = 0;
     if (i0 < i1) {
@@ -1760,7 +1943,8 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
     }
     int item = i0;
     while (item < i1) {
-      const int c = nt * 16 + col;
+      const int part = CPLX ? col & 1 : 0;
+      const int c = CPLX ? nt * 8 + (col >> 1) : nt * 16 + col;
       const bool colok = c < ncols;
       const int n0 = !colok ? 0 : MAXR == 1 ? c : c / nrhs;
       const int r = !colok || MAXR == 1 ? 0 : c - n0 * nrhs;
@@ -1772,14 +1956,18 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
         cs = cone_lookup(S, (unsigned long long)s_ch[o][n0] * S.ngrid + s_dist[k]);
         miss |= cs < 0;
       }
-      T br[SP::NK], bi[SP::NK];
-      small_load_b<PS, PA, T, MAXR>(Vc + ((int64_t)(cs >= 0 ? cs : 0) * nrhs + r) * P, kq, br, bi);
+      T br[SP::NK], bi[CPLX ? 1 : SP::NK];
+      const CT* vsrc = Vc + ((int64_t)(cs >= 0 ? cs : 0) * nrhs + r) * P;
+      if constexpr (CPLX)
+        small_load_b1<PS, PA, T, MAXR>(vsrc, kq, part, br);
+      else
+        small_load_b<PS, PA, T, MAXR>(vsrc, kq, br, bi);
       SplitB<SP::NK> sb;
-      if constexpr (SPLIT) split_b<SP::NK>((const float*)br, (const float*)bi, sb);
+      if constexpr (SPLIT) split_b<SP::NK>((const float*)br, (const float*)(CPLX ? br : bi), sb);
       do {
-        small_tile<PS, PA, T, MAXR, LREG, SPLIT>(s_L, s_u, A.cheb, wak, wbk, s_ratp, s_rows, s_y,
-                                                 rb, min(16, rend - rb), yb, colok, lane, br,
-                                                 bi, sb);
+        small_tile<PS, PA, T, MAXR, LREG, SPLIT, CPLX>(s_L, s_u, A.cheb, wak, wbk, s_ratp, s_rows,
+                                                       s_y, rb, min(16, rend - rb), yb, colok,
+                                                       lane, part, br, bi, sb);
         ++item;
         rb += 16;
       } while (item < i1 && rb < rend);
@@ -2176,6 +2364,32 @@ static hipError_t prop_level_impl(const ApplyArgs& A, int l, int kind,
   }
   prop_kernel<PS, PA, T, MAXR><<<nblk(Qh.ncones * P, 256), 256, 0, st>>>(A, l, Vc, Vp);
   return hipGetLastError();
+}
+
+int prop_table_record_bytes(int ps, int pa, int precision) {
+  const int P = ps * pa * pa;
+  if (P == 75) return precision == 0 ? OctRec<75, double>::kSize : OctRec<75, float>::kSize;
+  if (P == 18) return precision == 0 ? OctRec<18, double>::kSize : OctRec<18, float>::kSize;
+  if (P == 245) return 0;  // no matrix-core propagation at (5, 7)
+  return 0;
+}
+
+hipError_t launch_prop_table(const ApplyArgs& A, int l, int ps, int pa, int precision,
+                             int64_t ngroups, hipStream_t st) {
+  if (ngroups <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)(ngroups * 8);
+#define IFGF_PT(PS_, PA_)                                                           \
+  if (ps == PS_ && pa == PA_) {                                                     \
+    if (precision == 0)                                                             \
+      prop_table_kernel<PS_, PA_, double><<<blocks, 64, 0, st>>>(A, l);             \
+    else                                                                            \
+      prop_table_kernel<PS_, PA_, float><<<blocks, 64, 0, st>>>(A, l);              \
+    return hipGetLastError();                                                       \
+  }
+  IFGF_PT(3, 5)
+  IFGF_PT(2, 3)
+#undef IFGF_PT
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_prop_level(const ApplyArgs& A, int l, int ps, int pa,

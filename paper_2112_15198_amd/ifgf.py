@@ -38,7 +38,8 @@ class Opts(ctypes.Structure):
                 ("prop_kernel", ctypes.c_int), ("lookup", ctypes.c_int),
                 ("autotune", ctypes.c_int), ("cone_margin", ctypes.c_double),
                 ("leaf_max", ctypes.c_double), ("leaf_abs", ctypes.c_double),
-                ("grid_rule", ctypes.c_int), ("tune_cache", ctypes.c_char_p)]
+                ("grid_rule", ctypes.c_int), ("tune_cache", ctypes.c_char_p),
+                ("prop_tables", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -56,7 +57,7 @@ class Info(ctypes.Structure):
                 ("leaf_pairs", ctypes.c_int64),
                 ("near_pairs", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("plan_seconds", ctypes.c_double), ("tune_cache_hit", ctypes.c_int),
-                ("grid_doubling", ctypes.c_int)]
+                ("grid_doubling", ctypes.c_int), ("prop_table_bytes", ctypes.c_int64)]
 
 
 class StageTimes(ctypes.Structure):
@@ -119,7 +120,8 @@ GRID_RULES = {"auto": 0, "double": 1, "constant": 2, 0: 0, 1: 1, 2: 2}
 
 def _opts(precision, n_rhs, leaf_grid, levels, stages, host_only, device,
           cone_margin=None, prop_kernel=0, lookup=0, autotune=False,
-          leaf_max=0.0, leaf_abs=0.0, grid_rule="auto", tune_cache=None):
+          leaf_max=0.0, leaf_abs=0.0, grid_rule="auto", tune_cache=None,
+          prop_tables="auto"):
     o = Opts()
     _check(load_library().ifgf_default_opts(ctypes.byref(o)))
     o.precision = {"fp64": FP64, "fp32": FP32_MIXED, "mixed": FP32_MIXED,
@@ -142,6 +144,7 @@ def _opts(precision, n_rhs, leaf_grid, levels, stages, host_only, device,
     o.grid_rule = GRID_RULES[grid_rule] if grid_rule in GRID_RULES else int(grid_rule)
     # The plan copies the path at plan time.
     o.tune_cache = None if not tune_cache else os.fsencode(tune_cache)
+    o.prop_tables = {"auto": 0, "never": 1, "always": 2, 0: 0, 1: 1, 2: 2}[prop_tables]
     return o
 
 
@@ -208,7 +211,8 @@ class Plan:
                 "autotune_ms": [tuple(inf.autotune_ms[l]) for l in range(L)],
                 "near_pairs": inf.near_pairs, "device_bytes": inf.device_bytes,
                 "plan_seconds": inf.plan_seconds, "tune_cache_hit": bool(inf.tune_cache_hit),
-                "grid_doubling": bool(inf.grid_doubling)}
+                "grid_doubling": bool(inf.grid_doubling),
+                "prop_table_bytes": int(inf.prop_table_bytes)}
 
     def profile(self, enable=True):
         """Time every kernel launch of later applies with HIP events."""
@@ -270,7 +274,7 @@ def plan(points, kappa, p_s=3, p_ang=5, leaf_size=0.25, precision="fp64",
          n_rhs=1, leaf_grid=(2, 4, 8), levels=0, stages=3, host_only=False,
          device=None, cone_margin=None, prop_kernel="auto", lookup="auto",
          autotune=False, leaf_max=0.0, leaf_abs=0.0, grid_rule="auto",
-         tune_cache=None):
+         tune_cache=None, prop_tables="auto"):
     """Plan one instance; points is an (N, 3) float64 array on the host or a
     float64 CUDA tensor.
 
@@ -281,11 +285,13 @@ def plan(points, kappa, p_s=3, p_ang=5, leaf_size=0.25, precision="fp64",
     "medium" (four-wave); autotune=True times the four per level instead
     (tune_cache: a file that keeps the choices across plans).  kappa = 0
     (the Laplace kernel) needs leaf_abs (leaf side in length units) or
-    levels; leaf_max caps the leaf side in wavelengths."""
+    levels; leaf_max caps the leaf side in wavelengths.  prop_tables:
+    "auto", "never" or "always" keeps the box-independent propagation
+    geometry in plan-time tables (identical results)."""
     ptr, n, keep = _points_arg(points)
     o = _opts(precision, n_rhs, leaf_grid, levels, stages, host_only, device,
               cone_margin, prop_kernel, lookup, autotune, leaf_max, leaf_abs,
-              grid_rule, tune_cache)
+              grid_rule, tune_cache, prop_tables)
     h = ctypes.c_void_p()
     _check(load_library().ifgf_plan_ex(ctypes.byref(h), ptr, n, float(kappa), int(p_s),
                                        int(p_ang), float(leaf_size), ctypes.byref(o)))
@@ -297,7 +303,7 @@ def plan_batched(points_list, kappas, p_s=3, p_ang=5, leaf_size=0.25,
                  precision="fp64", n_rhs=1, leaf_grid=(2, 4, 8), levels=0,
                  stages=3, host_only=False, device=None, cone_margin=None,
                  prop_kernel="auto", lookup="auto", autotune=False, leaf_max=0.0,
-                 leaf_abs=0.0, grid_rule="auto", tune_cache=None):
+                 leaf_abs=0.0, grid_rule="auto", tune_cache=None, prop_tables="auto"):
     """Plan several independent instances evaluated together by each apply.
 
     Densities and outputs are (n_rhs, sum N_i), instances concatenated.
@@ -309,7 +315,7 @@ def plan_batched(points_list, kappas, p_s=3, p_ang=5, leaf_size=0.25,
     kap = np.ascontiguousarray(np.asarray(kappas, dtype=np.float64))
     o = _opts(precision, n_rhs, leaf_grid, levels, stages, host_only, device,
               cone_margin, prop_kernel, lookup, autotune, leaf_max, leaf_abs,
-              grid_rule, tune_cache)
+              grid_rule, tune_cache, prop_tables)
     h = ctypes.c_void_p()
     _check(load_library().ifgf_plan_batched(
         ctypes.byref(h), len(points_list), offsets.ctypes.data_as(ctypes.c_void_p),

@@ -313,6 +313,32 @@ def test_kernels_match_oracle_at_60k(n_rhs, precision, tol):
             assert_close(g[r][tg], fx["values"][r], tol, f"60k {prop} {precision} rhs {r}")
 
 
+@pytest.mark.parametrize("n_rhs", [1, 4])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_prop_tables_give_identical_results(precision, n_rhs):
+    """The wave-task propagation kernels read the box-independent octant
+    records (node geometry and grouping by child cone) from the plan-time
+    table or compute them per chunk; the records are made by the same device
+    code, so both paths give bit-identical outputs.  N = 60,000 sphere, both
+    task kernels forced on every level, 1 and 4 RHS; the tabled apply also
+    matches the oracle fixture."""
+    n = 60000
+    fx = _golden("ifgf_sphere_60k")
+    p = W.fibonacci_sphere(n)
+    k = W.kappa_sphere_10ppw(n)
+    a = W.densities(n, 4, 38)[:n_rhs]
+    for prop in ("small", "medium"):
+        say("prop tables", precision, prop, "rhs", n_rhs)
+        g0, i0 = run_gpu(p, a, k, precision=precision, prop_kernel=prop, prop_tables="never")
+        g1, i1 = run_gpu(p, a, k, precision=precision, prop_kernel=prop, prop_tables="always")
+        assert i0["prop_table_bytes"] == 0 and i1["prop_table_bytes"] > 0
+        assert np.array_equal(g0, g1), (prop, float(np.max(np.abs(g0 - g1))))
+        tol = 1e-10 if precision == "fp64" else 2e-5
+        for r in range(n_rhs):
+            assert_close(g1[r][fx["targets"]], fx["values"][r], tol,
+                         f"60k tables {prop} {precision} rhs {r}")
+
+
 @pytest.mark.parametrize("prop", ["grouped", "small", "medium"])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-6), ("bf16x3", 1e-6)])
 def test_graph_replays_match_eager(precision, tol, prop):
