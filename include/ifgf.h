@@ -127,8 +127,8 @@ typedef struct ifgf_opts {
   int prop_tables;  /* plan-time tables of the matrix-core propagation (the
                        node geometry of every parent cone index and child
                        octant, which does not depend on the box): 0 builds
-                       them for the steps nearest the leaves within the bytes
-                       of one cone-value buffer (at least 1 GiB), 1 never,
+                       them for the steps nearest the leaves within four times
+                       the bytes of one cone-value buffer (at least 1 GiB), 1 never,
                        2 for every step.  Results are identical either way. */
 } ifgf_opts;
 

@@ -319,14 +319,15 @@ static void autotune(ifgf_plan_s* P) {
 // by child cone) of every (instance, gamma') group of a step, so that the
 // apply reads it instead of recomputing it for every chunk of boxes.
 // Steps are taken from the leaf upwards (where groups hold the most boxes)
-// while the tables stay within the budget: the bytes of one cone-value
-// buffer (at least 1 GiB) with prop_tables = 0, none with 1, all with 2.
+// while the tables stay within the budget: four times the bytes of one
+// cone-value buffer (at least 1 GiB) with prop_tables = 0, none with 1, all
+// with 2.
 static void build_prop_tables(ifgf_plan_s* P, int64_t vbytes) {
   ApplyArgs& A = P->A;
   const int rec = prop_table_record_bytes(P->p_s, P->p_ang, P->opts.precision);
   if (rec <= 0 || P->opts.prop_tables == 1) return;
   const int64_t budget = P->opts.prop_tables == 2 ? INT64_MAX
-                                                   : std::max<int64_t>(vbytes, int64_t(1) << 30);
+                                                   : std::max<int64_t>(4 * vbytes, int64_t(1) << 30);
   int64_t used = 0;
   for (int l = 1; l < A.n_steps; ++l) {
     StepDev& Q = P->steps_h[l];

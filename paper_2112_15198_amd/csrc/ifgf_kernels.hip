@@ -1633,7 +1633,8 @@ __device__ __forceinline__ void small_tile(const T* s_L, const T* s_u, const Che
 // nm; the distinct child cones; the nodes grouped by child cone (rows:
 // node at grouped position, rbeg: first position of each child cone); the
 // M-tiles (child cone, first position); the local coordinates u of every
-// node in its child cone; the ratio G(x, x_k)/G(x, x_j) of every node.
+// node in its child cone; the ratio G(x, x_k)/G(x, x_j) of every node, in
+// node order and in grouped order.
 template <int P, typename T>
 struct OctRec {
   typedef typename C2<T>::type CT;
@@ -1645,7 +1646,8 @@ struct OctRec {
   static constexpr int kMr = kMk + P;                               // uchar[P]
   static constexpr int kU = (kMr + P + 15) / 16 * 16;               // T[3 P]
   static constexpr int kRat = (kU + 3 * P * (int)sizeof(T) + 15) / 16 * 16;  // CT[P]
-  static constexpr int kSize = (kRat + P * (int)sizeof(CT) + 15) / 16 * 16;
+  static constexpr int kRatg = kRat + P * (int)sizeof(CT);                   // CT[P]
+  static constexpr int kSize = (kRatg + P * (int)sizeof(CT) + 15) / 16 * 16;
   unsigned char* b;
   __device__ int& na() const { return *reinterpret_cast<int*>(b + kNa); }
   __device__ int& nm() const { return *reinterpret_cast<int*>(b + kNm); }
@@ -1656,6 +1658,7 @@ struct OctRec {
   __device__ unsigned char* mr() const { return b + kMr; }
   __device__ T* u() const { return reinterpret_cast<T*>(b + kU); }
   __device__ CT* ratp() const { return reinterpret_cast<CT*>(b + kRat); }
+  __device__ CT* ratg() const { return reinterpret_cast<CT*>(b + kRatg); }  // grouped order
 };
 
 // Node geometry of parent cone index (is, it, ip) of step l + 1 seen from
@@ -1742,6 +1745,9 @@ __device__ __forceinline__ void octant_grouping(const int* s_alpha, int lane,
     R.na() = na;
     R.nm() = nm;
   }
+  // The ratios in grouped order (LDS operations of one wave complete in
+  // order, so the rows written above are visible here).
+  for (int pos = lane; pos < P; pos += 64) R.ratg()[pos] = R.ratp()[rows[pos]];
 }
 
 // Plan-time table of a propagation step: one record per (group, octant),
@@ -1795,6 +1801,7 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
   // chunks hold few children per octant); several waves: (child, rhs)
   // columns with the real and imaginary parts in separate products.
   constexpr bool CPLX = NWV == 1;
+
   static_assert(P <= 128, "two nodes per lane");
   static_assert(NB <= 64, "one lane per box");
   typedef OctRec<P, T> Rec;
