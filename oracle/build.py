@@ -8,7 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 def library_path() -> str:
-    return os.path.join(HERE, "libifgf_oracle.so")
+    """The in-tree oracle library, or IFGF_ORACLE_PATH (a sanitized build)."""
+    return os.environ.get("IFGF_ORACLE_PATH") or os.path.join(HERE, "libifgf_oracle.so")
 
 
 def build() -> str:

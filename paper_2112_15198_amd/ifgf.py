@@ -12,7 +12,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libifgf.so")
+# IFGF_LIB_PATH selects another build of the library (the host-sanitized one
+# of build_sanitized.py); by default the in-tree libifgf.so.
+LIB_PATH = os.environ.get("IFGF_LIB_PATH") or os.path.join(HERE, "libifgf.so")
 
 IFGF_MAX_LEVELS = 24
 FP64, FP32_MIXED, FP32_BF16X3 = 0, 1, 2
