@@ -520,6 +520,130 @@ prop_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc,
   }
 }
 
+// Propagation from step l to step l + 1, one thread per (relevant parent
+// cone, node p), one wave per block, with the child cone values staged in
+// LDS: per child octant the lanes' child cones are collected (wave ballots;
+// the nodes of a parent cone fall into few child cones), up to kNodeBufs of
+// them are copied into LDS with contiguous loads, and each lane contracts its
+// cone's values from there (from global memory beyond kNodeBufs).
+static constexpr int kNodeBufs = 8;
+
+template <int PS, int PA, typename T, int MAXR>
+__global__ void __launch_bounds__(64)
+prop_node_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc,
+                 typename C2<T>::type* __restrict__ Vp) {
+  typedef typename C2<T>::type CT;
+  constexpr int P = PS * PA * PA;
+  __shared__ CT s_v[kNodeBufs][MAXR * P];
+  const StepDev& S = A.step[l];
+  const StepDev& Q = A.step[l + 1];
+  const int64_t n = Q.ncones * P;
+  const int64_t t0 = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * 64;
+  if (t0 >= n) return;  // the whole wave is past the end
+  const int lane = threadIdx.x;
+  const int64_t t = t0 + lane;
+  const bool active = t < n;
+  const int nrhs = A.nrhs;
+  const int64_t slot = active ? t / P : 0;
+  const int p = active ? (int)(t - slot * P) : 0;
+  const unsigned long long key = Q.cone_key[slot];
+  const int64_t j = (int64_t)(key / (unsigned long long)Q.ngrid);
+  const int64_t g = (int64_t)(key - (unsigned long long)j * Q.ngrid);
+  const int is = (int)(g / ((int64_t)Q.nt * Q.np));
+  const int it = (int)((g / Q.np) % Q.nt);
+  const int ip = (int)(g % Q.np);
+  const int a = p / (PA * PA), bb = (p / PA) % PA, cc = p % PA;
+  const int inst = Q.inst[j];
+  const double hp = Q.inst_h[inst];
+  const double hc = S.inst_h[inst];
+  const double kappa = A.inst_kappa[inst];
+  const double cjx = Q.center[3 * j], cjy = Q.center[3 * j + 1], cjz = Q.center[3 * j + 2];
+  double yp[3];
+  node_offset<PS, PA>(Q, hp, is, it, ip, a, bb, cc, yp);
+  double x0, x1, x2, rj;
+  {
+    IFGF_NO_CONTRACT
+    x0 = cjx + yp[0];
+    x1 = cjy + yp[1];
+    x2 = cjz + yp[2];
+    double e0 = x0 - cjx, e1 = x1 - cjy, e2 = x2 - cjz;
+    rj = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+  }
+  T accr[MAXR], acci[MAXR];
+#pragma unroll
+  for (int r = 0; r < MAXR; ++r) accr[r] = acci[r] = 0;
+  bool miss = false;  // a cone look-up missed (reported once, after the loop)
+  for (int o = 0; o < 8; ++o) {
+    const int k = active ? Q.child[8 * j + o] : -1;
+    int cslot = -1;
+    T Ls[PS], Lt[PA], Lp[PA];
+    T gc = 0, gs = 0;
+    if (k >= 0) {
+      double y0, y1, y2;
+      {
+        IFGF_NO_CONTRACT
+        y0 = x0 - S.center[3 * k];
+        y1 = x1 - S.center[3 * k + 1];
+        y2 = x2 - S.center[3 * k + 2];
+      }
+      ConeCoord c = cone_coord(S, hc, y0, y1, y2);
+      double u0, u1, u2;
+      const int cs = cone_index(c.q[0], S.ns, u0);
+      const int ct = cone_index(c.q[1], S.nt, u1);
+      const int cp = cone_index(c.q[2], S.np, u2);
+      const unsigned long long ckey = (unsigned long long)k * S.ngrid +
+                                      ((unsigned long long)cs * S.nt + ct) * S.np + cp;
+      cslot = cone_lookup(S, ckey);
+      miss |= cslot < 0;
+      lagrange<PS, T>((T)u0, A.cheb.ts, A.cheb.ws, Ls);
+      lagrange<PA, T>((T)u1, A.cheb.ta, A.cheb.wa, Lt);
+      lagrange<PA, T>((T)u2, A.cheb.ta, A.cheb.wa, Lp);
+      // G(x, x_k) / G(x, x_j) = (r_j / r_k) e^{i kappa (r_k - r_j)}.
+      expi<T>(kappa * (c.r - rj), gc, gs);
+      const T amp = (T)(rj / c.r);
+      gc *= amp;
+      gs *= amp;
+    }
+    // Stage the distinct child cones of the wave in LDS.
+    unsigned long long pend = __ballot(cslot >= 0);
+    if (pend == 0ull) continue;
+    int buf = -1, nb = 0;
+    while (pend) {
+      const int c = __shfl(cslot, __ffsll((long long)pend) - 1);
+      const bool mine = cslot == c;
+      if (nb < kNodeBufs) {
+        const CT* src = Vc + (int64_t)c * nrhs * P;
+        for (int i = lane; i < nrhs * P; i += 64) s_v[nb][i] = src[i];
+        if (mine) buf = nb;
+        ++nb;
+      }
+      pend &= ~__ballot(mine);
+    }
+    __syncthreads();  // one wave: the LDS copies are complete
+    if (cslot >= 0) {
+      const CT* vb = buf >= 0 ? nullptr : Vc + (int64_t)cslot * nrhs * P;
+      for (int r2 = 0; r2 < nrhs && r2 < MAXR; ++r2) {
+        T vr, vi;
+        if (buf >= 0)
+          contract<PS, PA, T>(&s_v[buf][r2 * P], Ls, Lt, Lp, vr, vi);
+        else
+          contract<PS, PA, T>(vb + r2 * P, Ls, Lt, Lp, vr, vi);
+        accr[r2] += vr * gc - vi * gs;
+        acci[r2] += vr * gs + vi * gc;
+      }
+    }
+    __syncthreads();  // the buffers are reused by the next octant
+  }
+  if (miss) atomicOr(A.err, 1);
+  if (!active) return;
+  for (int r2 = 0; r2 < nrhs && r2 < MAXR; ++r2) {
+    CT v;
+    v.x = accr[r2];
+    v.y = acci[r2];
+    Vp[(slot * nrhs + r2) * P + p] = v;
+  }
+}
+
 // Matrix-core (MFMA 16x16x4) operand layouts on gfx950, one wave:
 //   A (16 x 4):  lane l holds A[l % 16][l / 16]
 //   B (4 x 16):  lane l holds B[l / 16][l % 16]
@@ -2278,6 +2402,19 @@ int chunk_boxes(int precision, int nrhs) {
 // The grouped (matrix-core) propagation of one level: 512-thread blocks in
 // FP32, 256-thread blocks in FP64 (whose operands do not fit the former's
 // LDS layout).
+// The per-node propagation: the LDS-staged kernel (IFGF_NODE_GLOBAL selects
+// the plain per-node kernel, which reads every value from global memory).
+template <int PS, int PA, typename T, int MAXR>
+static void launch_prop_node(const ApplyArgs& A, int l, const typename C2<T>::type* Vc,
+                             typename C2<T>::type* Vp, int64_t ncones, hipStream_t st) {
+  constexpr int P = PS * PA * PA;
+#ifdef IFGF_NODE_GLOBAL
+  prop_kernel<PS, PA, T, MAXR><<<nblk(ncones * P, 256), 256, 0, st>>>(A, l, Vc, Vp);
+#else
+  prop_node_kernel<PS, PA, T, MAXR><<<nblk(ncones * P, 64), 64, 0, st>>>(A, l, Vc, Vp);
+#endif
+}
+
 template <int PS, int PA, typename T, int MAXR>
 static void launch_grouped(const ApplyArgs& A, int l, const typename C2<T>::type* Vc,
                            typename C2<T>::type* Vp, int64_t nchunks, hipStream_t st) {
@@ -2332,8 +2469,7 @@ static hipError_t apply_impl(const ApplyArgs& A, const void* dens_user,
           }
         }
         if (!done)
-          IFGF_TIMED(4, (prop_kernel<PS, PA, T, MAXR>
-                         <<<nblk(Qh.ncones * P, 256), 256, 0, st>>>(A, l, Vcur, Vnext)));
+          IFGF_TIMED(4, (launch_prop_node<PS, PA, T, MAXR>(A, l, Vcur, Vnext, Qh.ncones, st)));
         CT* tmp = Vcur;
         Vcur = Vnext;
         Vnext = tmp;
@@ -2369,7 +2505,7 @@ static hipError_t prop_level_impl(const ApplyArgs& A, int l, int kind,
       return hipGetLastError();
     }
   }
-  prop_kernel<PS, PA, T, MAXR><<<nblk(Qh.ncones * P, 256), 256, 0, st>>>(A, l, Vc, Vp);
+  launch_prop_node<PS, PA, T, MAXR>(A, l, Vc, Vp, Qh.ncones, st);
   return hipGetLastError();
 }
 
