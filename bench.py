@@ -371,7 +371,8 @@ def main():
     avg_ms = st[dom][0] / st[dom][1]
     bound = "alu"
     if dom in ("propagation", "propagation_mfma", "propagation_small"):
-        modes = {"propagation": (1,), "propagation_mfma": (2,), "propagation_small": (3, 4)}[dom]
+        modes = {"propagation": (1,), "propagation_mfma": (2,),
+                 "propagation_small": (3, 4, 5)}[dom]
         mode = modes[0]
         units = sum(pp for pp, md in zip(info["prop_pairs"], info["prop_mode"]) if md in modes)
         fpu = FLOP_PROP * flop_scale(P)

@@ -88,11 +88,13 @@ typedef struct ifgf_opts {
                        four-wave matrix-core tasks; >= 4: one-wave
                        matrix-core tasks; else per-node), 1 forces the
                        per-node form, 2 the matrix-core block form, 3 the
-                       one-wave task form, 4 the four-wave task form */
+                       one-wave task form, 4 the four-wave task form, 5 the
+                       four-wave task form with smaller chunks (40 boxes;
+                       four blocks per CU instead of three) */
   int lookup;       /* cone look-up: 0 dense tables where a level's table
                        (boxes x cone grid) has <= 2^28 entries, hash tables
                        elsewhere; 1 hash tables everywhere */
-  int autotune;     /* 1: at plan time, time the four propagation kernels
+  int autotune;     /* 1: at plan time, time the five propagation kernels
                        on every level where the matrix-core forms apply and
                        keep the fastest (overrides prop_kernel there) */
   double cone_margin; /* a point within cone_margin cone widths of a cone
@@ -151,9 +153,10 @@ typedef struct ifgf_info {
   int prop_mode[IFGF_MAX_LEVELS];      /* kernel of Propagation into step l:
                                          1 per-node, 2 matrix-core blocks,
                                          3 one-wave matrix-core tasks,
-                                         4 four-wave matrix-core tasks */
-  float autotune_ms[IFGF_MAX_LEVELS][4]; /* autotuner timings of Propagation
-                                         into step l, kernels 1..4 in order
+                                         4 four-wave matrix-core tasks,
+                                         5 four-wave tasks, smaller chunks */
+  float autotune_ms[IFGF_MAX_LEVELS][5]; /* autotuner timings of Propagation
+                                         into step l, kernels 1..5 in order
                                          (0 when not tuned) */
   int64_t leaf_pairs;     /* (leaf-cone node, source) evaluations of
                              LevelDEvaluations */

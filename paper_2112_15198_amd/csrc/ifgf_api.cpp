@@ -125,7 +125,7 @@ static ifgf_status validate(int p_s, int p_ang, const ifgf_opts& o) {
       return fail(IFGF_EINVAL, "leaf_grid entries must be in [1, 4096]");
   if (o.levels != 0 && o.levels < 3) return fail(IFGF_EINVAL, "levels must be 0 or >= 3");
   if (o.stages < 0 || o.stages > 3) return fail(IFGF_EINVAL, "stages must be in [0, 3]");
-  if (o.prop_kernel < 0 || o.prop_kernel > 4) return fail(IFGF_EINVAL, "prop_kernel must be 0..4");
+  if (o.prop_kernel < 0 || o.prop_kernel > 5) return fail(IFGF_EINVAL, "prop_kernel must be 0..5");
   if (o.lookup < 0 || o.lookup > 1) return fail(IFGF_EINVAL, "lookup must be 0 or 1");
   if (!(o.cone_margin >= 0.0 && o.cone_margin < 0.25))
     return fail(IFGF_EINVAL, "cone_margin must be in [0, 0.25)");
@@ -186,6 +186,7 @@ static std::string tune_key(ifgf_plan_s* P) {
     mix((uint64_t)S.nchunks);
     mix((uint64_t)S.nschunks);
     mix((uint64_t)S.nmchunks);
+    mix((uint64_t)S.nlchunks);
   }
   hipDeviceProp_t prop;
   std::string arch = "unknown";
@@ -265,7 +266,7 @@ static void autotune(ifgf_plan_s* P) {
     if (tune_cache_read(P->tune_cache, key, modes)) {
       for (int l = 1; l < A.n_steps; ++l) {
         StepDev& Q = P->steps_h[l];
-        if (modes[l] >= kPropNode && modes[l] <= kPropMedium && Q.ncones > 0 && Q.nchunks > 0)
+        if (modes[l] >= kPropNode && modes[l] < kPropKinds && Q.ncones > 0 && Q.nchunks > 0)
           Q.prop_grouped = modes[l];
       }
       P->info.tune_cache_hit = 1;
@@ -285,9 +286,9 @@ static void autotune(ifgf_plan_s* P) {
   for (int l = 0; l + 1 < A.n_steps; ++l) {
     StepDev& Q = P->steps_h[l + 1];
     if (Q.ncones == 0 || Q.nchunks == 0) continue;
-    float best[4] = {0, 0, 0, 0};
+    float best[kPropKinds] = {0, 0, 0, 0, 0};
     int pick = kPropNode;
-    for (int g = kPropNode; g <= kPropMedium; ++g) {
+    for (int g = kPropNode; g < kPropKinds; ++g) {
       HIP_TRY(launch_prop_level(A, l, P->p_s, P->p_ang, P->opts.precision, g, st));
       HIP_TRY(hipEventRecord(e0, st));
       for (int rep = 0; rep < 2; ++rep)
@@ -298,7 +299,7 @@ static void autotune(ifgf_plan_s* P) {
       if (best[g] < best[pick]) pick = g;
     }
     Q.prop_grouped = pick;
-    for (int g = 0; g < 4; ++g) P->info.autotune_ms[l + 1][g] = best[g] / 2;
+    for (int g = 0; g < kPropKinds; ++g) P->info.autotune_ms[l + 1][g] = best[g] / 2;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -500,6 +501,7 @@ static void build_device(ifgf_plan_s* P) {
       D.nchunks = 0;
       D.nschunks = 0;
       D.nmchunks = 0;
+      D.nlchunks = 0;
       D.ngroups = 0;
       D.prop_table = nullptr;
       if (l >= 1 && count > 0) {
@@ -519,8 +521,9 @@ static void build_device(ifgf_plan_s* P) {
         const int cbox = chunk_boxes(P->opts.precision, P->opts.n_rhs);
         const int sbox = small_chunk_boxes(P->opts.n_rhs, 1);
         const int mbox = small_chunk_boxes(P->opts.n_rhs, kMediumWaves);
-        std::vector<int64_t> cstart, sstart, mstart, gfirst;
-        std::vector<int32_t> clen, slen, mlen, sgroup, mgroup;
+        const int lbox = small_chunk_boxes(P->opts.n_rhs, kMediumWaves, kLeanBoxes);
+        std::vector<int64_t> cstart, sstart, mstart, lstart, gfirst;
+        std::vector<int32_t> clen, slen, mlen, llen, sgroup, mgroup, lgroup;
         int64_t groups = 0;
         for (int64_t i = 0; i < (int64_t)count; ++i) {
           bool same = i > 0 && gk(order[i]) == gk(order[i - 1]);
@@ -545,6 +548,12 @@ static void build_device(ifgf_plan_s* P) {
             mgroup.push_back((int32_t)(groups - 1));
           }
           mlen.back() += 1;
+          if (!same || llen.back() == lbox) {
+            lstart.push_back(i);
+            llen.push_back(0);
+            lgroup.push_back((int32_t)(groups - 1));
+          }
+          llen.back() += 1;
         }
         // Without the autotuner: the four-wave task kernel where many boxes
         // share a parent cone index (>= 32 on average), the one-wave task
@@ -555,6 +564,8 @@ static void build_device(ifgf_plan_s* P) {
         if (PP <= kMfmaMaxP) {
           if (mode == 2)
             D.prop_grouped = kPropGrouped;
+          else if (mode == 5)
+            D.prop_grouped = kPropLean;
           else if (mode == 4 || (mode == 0 && mean >= 32.0))
             D.prop_grouped = kPropMedium;
           else if (mode == 3 || (mode == 0 && mean >= 4.0))
@@ -594,6 +605,7 @@ static void build_device(ifgf_plan_s* P) {
           };
           box_order(sstart, slen, sgroup);
           box_order(mstart, mlen, mgroup);
+          box_order(lstart, llen, lgroup);
           D.schunk_start = P->upload(sstart);
           D.schunk_len = P->upload(slen);
           D.nschunks = (int64_t)sstart.size();
@@ -604,6 +616,10 @@ static void build_device(ifgf_plan_s* P) {
           D.group_first = P->upload(gfirst);
           D.schunk_group = P->upload(sgroup);
           D.mchunk_group = P->upload(mgroup);
+          D.lchunk_start = P->upload(lstart);
+          D.lchunk_len = P->upload(llen);
+          D.nlchunks = (int64_t)lstart.size();
+          D.lchunk_group = P->upload(lgroup);
         }
       }
       int64_t pairs_l = 0;

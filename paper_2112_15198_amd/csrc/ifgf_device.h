@@ -49,7 +49,7 @@ struct StepDev {
   // Propagation into this step, grouped: the relevant cones sorted by
   // (instance, gamma, box) and cut into chunks of boxes sharing one gamma,
   // whose node geometry is computed once per chunk.
-  int prop_grouped;           // kernel: kPropNode, kPropGrouped, kPropSmall or kPropMedium
+  int prop_grouped;           // kernel: kPropNode .. kPropLean
   int64_t nchunks;
   const int* gslot;           // slots in (instance, gamma, box) order
   const int64_t* chunk_start; // first index into gslot of each chunk
@@ -60,6 +60,9 @@ struct StepDev {
   int64_t nmchunks;           // ... and of small_chunk_boxes(nrhs, kMediumWaves)
   const int64_t* mchunk_start;
   const int* mchunk_len;
+  int64_t nlchunks;           // ... and of small_chunk_boxes(nrhs, kMediumWaves, kLeanBoxes)
+  const int64_t* lchunk_start;
+  const int* lchunk_len;
   // Groups: the runs of gslot sharing (instance, gamma).  The plan-time
   // table holds the box-independent record of every (group, octant)
   // (prop_table_record_bytes each, group-major), or is null.
@@ -67,13 +70,18 @@ struct StepDev {
   const int64_t* group_first; // first index into gslot of each group
   const int* schunk_group;    // group of each one-wave chunk
   const int* mchunk_group;    // group of each kMediumWaves-wave chunk
+  const int* lchunk_group;    // group of each lean kMediumWaves-wave chunk
   unsigned char* prop_table;
 };
 
 // Propagation kernels of a level: per node, matrix-core blocks, one-wave
-// matrix-core tasks, kMediumWaves-wave matrix-core tasks.
-enum { kPropNode = 0, kPropGrouped = 1, kPropSmall = 2, kPropMedium = 3 };
+// matrix-core tasks, kMediumWaves-wave matrix-core tasks, and the same with
+// chunks of kLeanBoxes boxes per wave (smaller blocks, four per CU).
+enum { kPropNode = 0, kPropGrouped = 1, kPropSmall = 2, kPropMedium = 3, kPropLean = 4,
+       kPropKinds = 5 };
 static constexpr int kMediumWaves = 4;
+static constexpr int kTaskBoxes = 16;  // boxes per wave of a task chunk (one RHS)
+static constexpr int kLeanBoxes = 10;  // ... of a lean task chunk
 
 // Largest P = P_s P_ang^2 with a matrix-core propagation kernel.
 static constexpr int kMfmaMaxP = 125;
@@ -82,9 +90,10 @@ static constexpr int kMfmaMaxP = 125;
 // sub-chunks of 32 (FP32) or 16 (FP64) GEMM columns.
 static constexpr int kSubChunks = 8;
 int chunk_boxes(int precision, int nrhs);
-// Boxes per chunk of the wave-task matrix-core propagation: 16 GEMM columns
-// per wave.
-int small_chunk_boxes(int nrhs, int waves);
+// Boxes per chunk of the wave-task matrix-core propagation: per_wave boxes
+// per wave with one RHS (kTaskBoxes: 16 GEMM columns), divided by kMaxRhs
+// with several.
+int small_chunk_boxes(int nrhs, int waves, int per_wave = kTaskBoxes);
 
 // Everything a kernel needs; passed by value (small), the per-step views
 // live in device memory.
@@ -155,8 +164,8 @@ int prop_table_record_bytes(int ps, int pa, int precision);
 // Fill the propagation table of step l + 1 (every group, every octant).
 hipError_t launch_prop_table(const ApplyArgs& A, int l, int ps, int pa, int precision,
                              int64_t ngroups, hipStream_t st);
-// One Propagation launch (step l -> l + 1) with kernel `kind` (kPropNode,
-// kPropGrouped, kPropSmall, kPropMedium), for timing at plan time;
+// One Propagation launch (step l -> l + 1) with kernel `kind` (kPropNode ..
+// kPropLean), for timing at plan time;
 // precision 0 FP64, 1 FP32-mixed, 2 FP32 with the three-term BF16 product.
 hipError_t launch_prop_level(const ApplyArgs& A, int l, int ps, int pa,
                              int precision, int kind, hipStream_t st);

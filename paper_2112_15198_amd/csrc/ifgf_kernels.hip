@@ -1480,7 +1480,6 @@ struct SmallProp {
   static constexpr int NE = PA > 4 ? PA - 4 : 0;  // groups with b = 4 + e, a = kq
   static constexpr int NG = PS + NE;
   static constexpr int NK = NG * PA;          // k-steps (g, c)
-  static constexpr int WB = 16 / MAXR;        // boxes per wave
   static constexpr int NAMAX = 8;             // child cones per octant with a cached slot
   // s_L row: the slot products L_a L_b at kq NG + g, then L_c; 16 bytes.
   static constexpr int LW = (4 * NG + PA + 3) / 4 * 4;
@@ -1912,14 +1911,14 @@ __global__ void __launch_bounds__(64) prop_table_kernel(ApplyArgs A, int l) {
 // contiguous ranges, one per wave.  Within an octant every (box, node) is
 // written by exactly one item (M-tiles of different child cones hold
 // different nodes), so the block-wide accumulators need no atomics.
-template <int PS, int PA, typename T, int MAXR, int NWV, bool SPLIT>
-__global__ void __launch_bounds__(64 * NWV, sizeof(T) == 4 ? 3 : 2)
+template <int PS, int PA, typename T, int MAXR, int NWV, bool SPLIT, int BPW = kTaskBoxes>
+__global__ void __launch_bounds__(64 * NWV, sizeof(T) == 4 ? (BPW < kTaskBoxes ? 4 : 3) : 2)
 prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc,
                   typename C2<T>::type* __restrict__ Vp) {
   typedef SmallProp<PS, PA, T, MAXR> SP;
   typedef typename C2<T>::type CT;
   constexpr int P = SP::P, NAMAX = SP::NAMAX, LW = SP::LW;
-  constexpr int NB = NWV * SP::WB;          // boxes per block
+  constexpr int NB = NWV * (BPW / MAXR);    // boxes per block
   constexpr bool LREG = NWV == 1;           // factors in registers (one wave)
   // One wave: (child, rhs, part) columns, 8 complex columns per N-tile (its
   // chunks hold few children per octant); several waves: (child, rhs)
@@ -1955,14 +1954,17 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
   const StepDev& Q = A.step[l + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nrhs = A.nrhs;
-  const int64_t* cstart = NWV == 1 ? Q.schunk_start : Q.mchunk_start;
-  const int* clen = NWV == 1 ? Q.schunk_len : Q.mchunk_len;
+  constexpr bool LEAN = NWV > 1 && BPW < kTaskBoxes;
+  const int64_t* cstart = NWV == 1 ? Q.schunk_start : LEAN ? Q.lchunk_start : Q.mchunk_start;
+  const int* clen = NWV == 1 ? Q.schunk_len : LEAN ? Q.lchunk_len : Q.mchunk_len;
   const int64_t g0 = cstart[blockIdx.x];
   const int nb = clen[blockIdx.x];          // boxes of this chunk, <= NB
   // The step's table of octant records, and this chunk's group in it.
   const unsigned char* const table =
       Q.prop_table ? Q.prop_table +
-                         (int64_t)(NWV == 1 ? Q.schunk_group : Q.mchunk_group)[blockIdx.x] * 8 *
+                         (int64_t)(NWV == 1 ? Q.schunk_group
+                                   : LEAN   ? Q.lchunk_group
+                                            : Q.mchunk_group)[blockIdx.x] * 8 *
                              Rec::kSize
                    : nullptr;
   const unsigned long long key0 = Q.cone_key[Q.gslot[g0]];
@@ -2391,7 +2393,9 @@ hipError_t sort_keys(unsigned long long* keys, unsigned long long* tmp,
     }                                                              \
   } while (0)
 
-int small_chunk_boxes(int nrhs, int waves) { return waves * (16 / (nrhs <= 1 ? 1 : kMaxRhs)); }
+int small_chunk_boxes(int nrhs, int waves, int per_wave) {
+  return waves * (per_wave / (nrhs <= 1 ? 1 : kMaxRhs));
+}
 
 int chunk_boxes(int precision, int nrhs) {
   const int maxr = nrhs <= 1 ? 1 : kMaxRhs;
@@ -2466,6 +2470,11 @@ static hipError_t apply_impl(const ApplyArgs& A, const void* dens_user,
                            <<<(unsigned)Qh.nmchunks, 64 * kMediumWaves, 0, st>>>(A, l, Vcur,
                                                                                  Vnext)));
             done = true;
+          } else if (Qh.prop_grouped == kPropLean) {
+            IFGF_TIMED(7, (prop_small_kernel<PS, PA, T, MAXR, kMediumWaves, SPLIT, kLeanBoxes>
+                           <<<(unsigned)Qh.nlchunks, 64 * kMediumWaves, 0, st>>>(A, l, Vcur,
+                                                                                 Vnext)));
+            done = true;
           }
         }
         if (!done)
@@ -2497,6 +2506,11 @@ static hipError_t prop_level_impl(const ApplyArgs& A, int l, int kind,
     }
     if (kind == kPropSmall && Qh.nschunks > 0) {
       prop_small_kernel<PS, PA, T, MAXR, 1, SPLIT><<<(unsigned)Qh.nschunks, 64, 0, st>>>(A, l, Vc, Vp);
+      return hipGetLastError();
+    }
+    if (kind == kPropLean && Qh.nlchunks > 0) {
+      prop_small_kernel<PS, PA, T, MAXR, kMediumWaves, SPLIT, kLeanBoxes>
+          <<<(unsigned)Qh.nlchunks, 64 * kMediumWaves, 0, st>>>(A, l, Vc, Vp);
       return hipGetLastError();
     }
     if (kind == kPropMedium && Qh.nmchunks > 0) {

@@ -55,7 +55,7 @@ class Info(ctypes.Structure):
                 ("grid", ctypes.c_int64 * IFGF_MAX_LEVELS),
                 ("prop_pairs", ctypes.c_int64 * IFGF_MAX_LEVELS),
                 ("prop_mode", ctypes.c_int * IFGF_MAX_LEVELS),
-                ("autotune_ms", (ctypes.c_float * 4) * IFGF_MAX_LEVELS),
+                ("autotune_ms", (ctypes.c_float * 5) * IFGF_MAX_LEVELS),
                 ("leaf_pairs", ctypes.c_int64),
                 ("near_pairs", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("plan_seconds", ctypes.c_double), ("tune_cache_hit", ctypes.c_int),
@@ -138,7 +138,7 @@ def _opts(precision, n_rhs, leaf_grid, levels, stages, host_only, device,
     if cone_margin is not None:
         o.cone_margin = float(cone_margin)
     o.prop_kernel = {"auto": 0, "node": 1, "grouped": 2, "small": 3, "medium": 4,
-                     0: 0, 1: 1, 2: 2, 3: 3, 4: 4}[prop_kernel]
+                     "lean": 5, 0: 0, 1: 1, 2: 2, 3: 3, 4: 4, 5: 5}[prop_kernel]
     o.lookup = {"auto": 0, "hash": 1, 0: 0, 1: 1}[lookup]
     o.autotune = 1 if autotune else 0
     o.leaf_max = float(leaf_max)
@@ -283,8 +283,9 @@ def plan(points, kappa, p_s=3, p_ang=5, leaf_size=0.25, precision="fp64",
     precision: "fp64" (IFGF_FP64, complex128 densities), "fp32"
     (IFGF_FP32_MIXED, complex64) or "bf16x3" (IFGF_FP32_BF16X3, complex64:
     FP32-mixed with the wave-task propagation product in three-term BF16
-    form).  prop_kernel: "auto", "node", "grouped", "small" (one-wave) or
-    "medium" (four-wave); autotune=True times the four per level instead
+    form).  prop_kernel: "auto", "node", "grouped", "small" (one-wave),
+    "medium" (four-wave) or "lean" (four-wave, smaller chunks); autotune=True
+    times the five per level instead
     (tune_cache: a file that keeps the choices across plans).  kappa = 0
     (the Laplace kernel) needs leaf_abs (leaf side in length units) or
     levels; leaf_max caps the leaf side in wavelengths.  prop_tables:

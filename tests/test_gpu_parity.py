@@ -152,7 +152,7 @@ def test_other_orders_match_oracle(ps, pa):
     assert_close(g[0], o, 1e-10, f"fp64 order {ps},{pa}")
 
 
-@pytest.mark.parametrize("prop", ["auto", "grouped", "small", "medium", "node"])
+@pytest.mark.parametrize("prop", ["auto", "grouped", "small", "medium", "lean", "node"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
 def test_multi_rhs_equals_single_rhs(precision, prop):
     n = 6000
@@ -272,7 +272,7 @@ def test_relevant_cones_match_oracle_exactly(geom):
 @pytest.mark.parametrize("prop,lookup", [("node", "auto"), ("grouped", "auto"),
                                          ("grouped", "hash"), ("node", "hash"),
                                          ("small", "auto"), ("small", "hash"),
-                                         ("medium", "auto")])
+                                         ("medium", "auto"), ("lean", "auto")])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 2e-5), ("bf16x3", 2e-5)])
 def test_kernel_variants_match_oracle(prop, lookup, precision, tol):
     """Per-node, matrix-core block and wave-task (one and four waves)
@@ -304,7 +304,7 @@ def test_kernels_match_oracle_at_60k(n_rhs, precision, tol):
     k = W.kappa_sphere_10ppw(n)
     a = W.densities(n, 4, 38)[:n_rhs]
     tg = fx["targets"]
-    for prop, mode in (("node", 1), ("small", 3), ("medium", 4), ("auto", None)):
+    for prop, mode in (("node", 1), ("small", 3), ("medium", 4), ("lean", 5), ("auto", None)):
         say("60k vs oracle fixture", precision, prop, "rhs", n_rhs)
         g, info = run_gpu(p, a, k, precision=precision, prop_kernel=prop)
         if mode is not None:
@@ -327,7 +327,7 @@ def test_prop_tables_give_identical_results(precision, n_rhs):
     p = W.fibonacci_sphere(n)
     k = W.kappa_sphere_10ppw(n)
     a = W.densities(n, 4, 38)[:n_rhs]
-    for prop in ("small", "medium"):
+    for prop in ("small", "medium", "lean"):
         say("prop tables", precision, prop, "rhs", n_rhs)
         g0, i0 = run_gpu(p, a, k, precision=precision, prop_kernel=prop, prop_tables="never")
         g1, i1 = run_gpu(p, a, k, precision=precision, prop_kernel=prop, prop_tables="always")
@@ -339,7 +339,7 @@ def test_prop_tables_give_identical_results(precision, n_rhs):
                          f"60k tables {prop} {precision} rhs {r}")
 
 
-@pytest.mark.parametrize("prop", ["grouped", "small", "medium"])
+@pytest.mark.parametrize("prop", ["grouped", "small", "medium", "lean"])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-6), ("bf16x3", 1e-6)])
 def test_graph_replays_match_eager(precision, tol, prop):
     """The HIP-graph apply, replayed several times with eager work and
@@ -384,7 +384,7 @@ def test_autotune_picks_a_kernel_per_level_and_stays_exact():
     for l in tuned:
         t = info["autotune_ms"][l]
         assert all(x > 0 for x in t), t
-        assert info["prop_mode"][l] == 1 + min(range(4), key=lambda g: t[g])
+        assert info["prop_mode"][l] == 1 + min(range(len(t)), key=lambda g: t[g])
     o = oracle.ifgf(p, a[0], k, leaf_grid=(2, 4, 8))
     assert_close(g[0], o, 1e-10, "autotuned")
 
@@ -440,7 +440,7 @@ def test_tuning_cache_reuses_choices(tmp_path):
     g2, i2 = run_gpu(p, a, k, precision="fp32", autotune=True, tune_cache=cache)
     assert not i1["tune_cache_hit"] and i2["tune_cache_hit"]
     assert i1["prop_mode"] == i2["prop_mode"]
-    assert all(t == (0, 0, 0, 0) for t in i2["autotune_ms"])
+    assert all(all(x == 0 for x in t) for t in i2["autotune_ms"])
     np.testing.assert_array_equal(g1, g2)
     lines = open(cache).read().splitlines()
     assert len(lines) == 1 and "| modes=" in lines[0]
