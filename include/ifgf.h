@@ -131,7 +131,9 @@ typedef struct ifgf_opts {
                        octant, which does not depend on the box): 0 builds
                        them for the steps nearest the leaves within four times
                        the bytes of one cone-value buffer (at least 1 GiB), 1 never,
-                       2 for every step.  Results are identical either way. */
+                       2 for every step; 0 and 2 leave a tenth of the device
+                       memory (at least 4 GiB) free.  Results are identical
+                       either way. */
 } ifgf_opts;
 
 /* Size information about a plan (ifgf_plan_info). */

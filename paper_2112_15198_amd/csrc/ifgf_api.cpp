@@ -327,8 +327,14 @@ static void build_prop_tables(ifgf_plan_s* P, int64_t vbytes) {
   ApplyArgs& A = P->A;
   const int rec = prop_table_record_bytes(P->p_s, P->p_ang, P->opts.precision);
   if (rec <= 0 || P->opts.prop_tables == 1) return;
-  const int64_t budget = P->opts.prop_tables == 2 ? INT64_MAX
-                                                   : std::max<int64_t>(4 * vbytes, int64_t(1) << 30);
+  int64_t budget = P->opts.prop_tables == 2 ? INT64_MAX
+                                             : std::max<int64_t>(4 * vbytes, int64_t(1) << 30);
+  // The tables only save work: they never take the device's last memory (a
+  // tenth of it, at least 4 GiB, stays free for the caller).
+  size_t free_b = 0, total_b = 0;
+  HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+  const int64_t reserve = std::max<int64_t>((int64_t)(total_b / 10), int64_t(4) << 30);
+  budget = std::min<int64_t>(budget, std::max<int64_t>(0, (int64_t)free_b - reserve));
   int64_t used = 0;
   for (int l = 1; l < A.n_steps; ++l) {
     StepDev& Q = P->steps_h[l];
@@ -413,6 +419,20 @@ static void build_device(ifgf_plan_s* P) {
     D.s_node = P->upload(sn);
     D.t_node = P->upload(tn);
     D.p_node = P->upload(pn);
+    D.rds = 1.0 / D.ds;
+    D.rdt = 1.0 / D.dt;
+    D.rdp = 1.0 / D.dp;
+    std::vector<double> tb((size_t)(D.nt + 1) * 2), pb((size_t)(D.np + 1) * 2);
+    for (int i = 0; i <= D.nt; ++i) {
+      tb[2 * (size_t)i] = std::cos(D.dt * i);
+      tb[2 * (size_t)i + 1] = std::sin(D.dt * i);
+    }
+    for (int i = 0; i <= D.np; ++i) {
+      pb[2 * (size_t)i] = std::cos(D.dp * i);
+      pb[2 * (size_t)i + 1] = std::sin(D.dp * i);
+    }
+    D.t_bnd = P->upload(tb);
+    D.p_bnd = P->upload(pb);
     D.ncones = 0;
   }
   P->steps_d = P->dalloc<StepDev>(std::max(L, 1));

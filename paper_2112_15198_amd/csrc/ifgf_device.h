@@ -38,6 +38,9 @@ struct StepDev {
   const double* s_node;       // ns * P_s node values of s
   const double* t_node;       // nt * P_ang (sin, cos) of theta at the nodes
   const double* p_node;       // np * P_ang (sin, cos) of phi at the nodes
+  double rds, rdt, rdp;       // 1/ds, 1/dt, 1/dp
+  const double* t_bnd;        // (cos, sin) of the theta boundaries i dt, i = 0..nt
+  const double* p_bnd;        // (cos, sin) of the phi boundaries i dp, i = 0..np
   // Relevant cone segments, sorted by key = box * ngrid + gamma (the order
   // "box Morton order, then radial, elevation, azimuth").
   int64_t ncones;

@@ -108,6 +108,117 @@ __device__ __forceinline__ int cone_index(double q, int n, double& u) {
   return i;
 }
 
+// Cone selection of the apply: the cone index gamma of y = x - x_k, its local
+// coordinates u in [-1, 1]^3 and r = |y| with 1/r.
+struct ConeSel {
+  int64_t gamma;
+  double r, rinv;
+};
+
+// atan2(y, x) to about 1.2e-5 rad, as the first guess of a cone index:
+// octant reduction and the odd polynomial of Abramowitz and Stegun 4.4.49
+// on [0, 1].
+__device__ __forceinline__ float atan2_est(float y, float x) {
+  const float ax = fabsf(x), ay = fabsf(y);
+  const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+  const float a = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
+  const float s = a * a;
+  float r = a * (0.9998660f +
+                 s * (-0.3302995f + s * (0.1801410f + s * (-0.0851330f + s * 0.0208351f))));
+  if (ay > ax) r = 1.57079633f - r;
+  if (x < 0.0f) r = 3.14159265f - r;
+  return y < 0.0f ? -r : r;
+}
+
+// One angle of the FP32-mixed cone selection.  The angle is atan2(Y, X),
+// est an estimate of it (>= 0) and bnd the (cos, sin) of the cone
+// boundaries beta_i = i w, i = 0..n.  The estimate's cone is confirmed, or
+// moved, with FP64 side tests, sin(angle - beta) r = Y cos(beta) - X sin(beta),
+// so that the index is floor(angle / w) except at rounding distance from a
+// boundary (where the relevant-cone marking also holds the neighbour); the
+// local coordinate comes from the FP32 angle between the point and the
+// cone's lower boundary.
+__device__ __forceinline__ int angle_select(double X, double Y, float est, double rw, int n,
+                                            bool periodic, const double* bnd, float& u) {
+  IFGF_NO_CONTRACT
+  const double2* b2 = reinterpret_cast<const double2*>(bnd);
+  int i = min((int)(est * (float)rw), n - 1);
+  // Boundaries i and i + 1, loaded together (the table has n + 1 entries).
+  const double2 b0 = b2[i], b1 = b2[i + 1];
+  double cb = b0.x, sb = b0.y;
+  double d = Y * cb - X * sb;
+  const double d1 = Y * b1.x - X * b1.y;
+  if (d < 0.0) {
+    // Rare: the estimate is too high (by one cone unless the cones are
+    // narrower than its error).
+    for (int m = 0; m < n && d < 0.0; ++m) {
+      if (i > 0)
+        --i;
+      else if (periodic)
+        i = n - 1;
+      else
+        break;
+      cb = b2[i].x;
+      sb = b2[i].y;
+      d = Y * cb - X * sb;
+    }
+  } else if (d1 > 0.0 && i + 1 < n) {
+    // Rare: the estimate is too low.
+    ++i;
+    cb = b1.x;
+    sb = b1.y;
+    d = d1;
+    while (i + 1 < n) {
+      const double2 bn = b2[i + 1];
+      if (!(Y * bn.x - X * bn.y > 0.0)) break;
+      ++i;
+      cb = bn.x;
+      sb = bn.y;
+      d = Y * cb - X * sb;
+    }
+  }
+  const double c = X * cb + Y * sb;
+  u = atan2f((float)d, (float)c) * (float)(2.0 * rw) - 1.0f;
+  return i;
+}
+
+// FP64 mode: cone_coord and cone_index (the rounding path of the relevant-cone
+// marking).  FP32-mixed: r, s and the side tests in FP64, the angles'
+// estimates and local coordinates in FP32 (the two FP64 arctangents are most
+// of the geometry's cost in the per-node propagation).
+template <typename T>
+__device__ __forceinline__ ConeSel cone_select(const StepDev& S, double h, double y0, double y1,
+                                               double y2, T u[3]);
+template <>
+__device__ __forceinline__ ConeSel cone_select<double>(const StepDev& S, double h, double y0,
+                                                       double y1, double y2, double u[3]) {
+  const ConeCoord c = cone_coord(S, h, y0, y1, y2);
+  const int is = cone_index(c.q[0], S.ns, u[0]);
+  const int it = cone_index(c.q[1], S.nt, u[1]);
+  const int ip = cone_index(c.q[2], S.np, u[2]);
+  return ConeSel{((int64_t)is * S.nt + it) * S.np + ip, c.r, 1.0 / c.r};
+}
+template <>
+__device__ __forceinline__ ConeSel cone_select<float>(const StepDev& S, double h, double y0,
+                                                      double y1, double y2, float u[3]) {
+  IFGF_NO_CONTRACT
+  ConeSel c;
+  const double rho2 = y0 * y0 + y1 * y1;
+  c.r = sqrt(rho2 + y2 * y2);
+  c.rinv = 1.0 / c.r;
+  double u0;
+  const int is = cone_index(h * c.rinv * S.rds, S.ns, u0);
+  u[0] = (float)u0;
+  const double rho = sqrt(rho2);
+  const float th = atan2_est((float)rho, (float)y2);
+  float ph = atan2_est((float)y1, (float)y0);
+  if (ph < 0.0f) ph += (float)(2.0 * kPiD);
+  const int it = angle_select(y2, rho, th, S.rdt, S.nt, false, S.t_bnd, u[1]);
+  const int ip = angle_select(y0, y1, ph, S.rdp, S.np, true, S.p_bnd, u[2]);
+  c.gamma = ((int64_t)is * S.nt + it) * S.np + ip;
+  return c;
+}
+
 // Position of interpolation node (a, b, c) of cone (is, it, ip), relative to
 // the centre of its box: (h/s) (sin th cos ph, sin th sin ph, cos th).
 template <int PS, int PA>
@@ -203,6 +314,35 @@ __device__ __forceinline__ void expi<float>(double phase, float& c, float& s) {
 // ---------------------------------------------------------------------------
 
 // Densities, user layout [rhs][N] -> sorted layout [i][rhs].
+// Geometry of node p of parent cone index (is, it, ip) of step l + 1 seen
+// from the child in octant o (child box centre at +-H_c/2 per axis from the
+// parent's): the child cone alpha, the local coordinates u and the ratio
+// G(x_p, x_k)/G(x_p, x_j) (phase reduced in FP64).  Box-independent.
+template <int PS, int PA, typename T>
+__device__ __forceinline__ int node_octant_geometry(const StepDev& S, const StepDev& Q, double hp,
+                                                    double hc, double Hc, double kappa, int is,
+                                                    int it, int ip, int o, int p, T u[3],
+                                                    typename C2<T>::type& rat) {
+  const int a = p / (PA * PA), bb = (p / PA) % PA, cc = p % PA;
+  double yp[3];
+  node_offset<PS, PA>(Q, hp, is, it, ip, a, bb, cc, yp);
+  double y0, y1, y2, rj;
+  {
+    IFGF_NO_CONTRACT
+    y0 = yp[0] - (((o >> 2) & 1) ? 0.5 * Hc : -0.5 * Hc);
+    y1 = yp[1] - (((o >> 1) & 1) ? 0.5 * Hc : -0.5 * Hc);
+    y2 = yp[2] - ((o & 1) ? 0.5 * Hc : -0.5 * Hc);
+    rj = sqrt(yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]);
+  }
+  const ConeSel cr = cone_select<T>(S, hc, y0, y1, y2, u);
+  T gcv, gsv;
+  expi<T>(kappa * (cr.r - rj), gcv, gsv);
+  const T amp = (T)(rj * cr.rinv);
+  rat.x = gcv * amp;
+  rat.y = gsv * amp;
+  return (int)cr.gamma;
+}
+
 template <typename T>
 __global__ void perm_in_kernel(const typename C2<T>::type* __restrict__ in,
                                typename C2<T>::type* __restrict__ out,
@@ -365,66 +505,89 @@ leaf_eval_kernel(ApplyArgs A, typename C2<T>::type* __restrict__ V) {
   }
 }
 
-// Interpolation(d) at step l: one thread per target point.
+// Interpolation(d) at step l: blocks of kInterpParts waves over the same 64
+// target points (one per lane), wave w summing the cousin boxes w,
+// w + kInterpParts, ... of each target's list; the parts are added in LDS.
+// The lanes of a wave still walk their (mostly shared) cousin list in step,
+// so a gather instruction touches few cones, and the launch has
+// kInterpParts times the waves of one wave per 64 targets.
+static constexpr int kInterpParts = 4;
+
 template <int PS, int PA, typename T, int MAXR>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64 * kInterpParts)
 interp_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V,
               typename C2<T>::type* __restrict__ out) {
+  typedef typename C2<T>::type CT;
   constexpr int P = PS * PA * PA;
-  int64_t i = gtid();
-  if (i >= A.n) return;
+  __shared__ CT s_acc[kInterpParts - 1][MAXR][64];
+  const int lane = threadIdx.x & 63, part = threadIdx.x >> 6;
+  const int64_t i = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * 64 + lane;
   const StepDev& S = A.step[l];
-  int b = S.pt_box[i];
-  if (b < 0) return;
-  int inst = S.inst[b];
-  double h = S.inst_h[inst];
-  double kappa = A.inst_kappa[inst];
-  double xi = A.x[i], yi = A.y[i], zi = A.z[i];
+  const int b = i < A.n ? S.pt_box[i] : -1;
   T accr[MAXR], acci[MAXR];
 #pragma unroll
   for (int r = 0; r < MAXR; ++r) accr[r] = acci[r] = 0;
   bool miss = false;  // a cone look-up missed (reported once, after the loop)
-  for (int64_t j = S.cous_begin[b]; j < S.cous_begin[b + 1]; ++j) {
-    int k = S.cous[j];
-    double y0, y1, y2;
-    {
-      IFGF_NO_CONTRACT
-      y0 = xi - S.center[3 * k];
-      y1 = yi - S.center[3 * k + 1];
-      y2 = zi - S.center[3 * k + 2];
-    }
-    ConeCoord cc = cone_coord(S, h, y0, y1, y2);
-    double u0, u1, u2;
-    int is = cone_index(cc.q[0], S.ns, u0);
-    int it = cone_index(cc.q[1], S.nt, u1);
-    int ip = cone_index(cc.q[2], S.np, u2);
-    unsigned long long key = (unsigned long long)k * S.ngrid +
-                             ((unsigned long long)is * S.nt + it) * S.np + ip;
-    int slot = cone_lookup(S, key);
-    if (slot < 0) {
-      miss = true;
-      continue;
-    }
-    T Ls[PS], Lt[PA], Lp[PA];
-    lagrange<PS, T>((T)u0, A.cheb.ts, A.cheb.ws, Ls);
-    lagrange<PA, T>((T)u1, A.cheb.ta, A.cheb.wa, Lt);
-    lagrange<PA, T>((T)u2, A.cheb.ta, A.cheb.wa, Lp);
-    T gc, gs;
-    expi<T>(kappa * cc.r, gc, gs);
-    T amp = (T)(0.25 / (kPiD * cc.r));
-    gc *= amp;
-    gs *= amp;
-    const typename C2<T>::type* vb = V + (int64_t)slot * A.nrhs * P;
-    for (int r2 = 0; r2 < A.nrhs && r2 < MAXR; ++r2) {
-      T vr, vi;
-      contract<PS, PA, T>(vb + r2 * P, Ls, Lt, Lp, vr, vi);
-      accr[r2] += vr * gc - vi * gs;
-      acci[r2] += vr * gs + vi * gc;
+  if (b >= 0) {
+    const int inst = S.inst[b];
+    const double h = S.inst_h[inst];
+    const double kappa = A.inst_kappa[inst];
+    const double xi = A.x[i], yi = A.y[i], zi = A.z[i];
+    for (int64_t j = S.cous_begin[b] + part; j < S.cous_begin[b + 1]; j += kInterpParts) {
+      const int k = S.cous[j];
+      double y0, y1, y2;
+      {
+        IFGF_NO_CONTRACT
+        y0 = xi - S.center[3 * k];
+        y1 = yi - S.center[3 * k + 1];
+        y2 = zi - S.center[3 * k + 2];
+      }
+      // FP64 selection in both modes: the FP32 one's boundary-table loads
+      // would sit between the geometry and the look-up in this latency-bound
+      // loop.
+      double u[3];
+      const ConeSel cc = cone_select<double>(S, h, y0, y1, y2, u);
+      const unsigned long long key =
+          (unsigned long long)k * S.ngrid + (unsigned long long)cc.gamma;
+      const int slot = cone_lookup(S, key);
+      if (slot < 0) {
+        miss = true;
+        continue;
+      }
+      T Ls[PS], Lt[PA], Lp[PA];
+      lagrange<PS, T>((T)u[0], A.cheb.ts, A.cheb.ws, Ls);
+      lagrange<PA, T>((T)u[1], A.cheb.ta, A.cheb.wa, Lt);
+      lagrange<PA, T>((T)u[2], A.cheb.ta, A.cheb.wa, Lp);
+      T gc, gs;
+      expi<T>(kappa * cc.r, gc, gs);
+      const T amp = (T)((0.25 / kPiD) * cc.rinv);
+      gc *= amp;
+      gs *= amp;
+      const CT* vb = V + (int64_t)slot * A.nrhs * P;
+      for (int r2 = 0; r2 < A.nrhs && r2 < MAXR; ++r2) {
+        T vr, vi;
+        contract<PS, PA, T>(vb + r2 * P, Ls, Lt, Lp, vr, vi);
+        accr[r2] += vr * gc - vi * gs;
+        acci[r2] += vr * gs + vi * gc;
+      }
     }
   }
   if (miss) atomicOr(A.err, 1);
+  if (part > 0) {
+#pragma unroll
+    for (int r = 0; r < MAXR; ++r) s_acc[part - 1][r][lane] = CT{accr[r], acci[r]};
+  }
+  __syncthreads();
+  if (part > 0 || b < 0) return;
+#pragma unroll
+  for (int q = 0; q < kInterpParts - 1; ++q)
+#pragma unroll
+    for (int r = 0; r < MAXR; ++r) {
+      accr[r] += s_acc[q][r][lane].x;
+      acci[r] += s_acc[q][r][lane].y;
+    }
   for (int r2 = 0; r2 < A.nrhs && r2 < MAXR; ++r2) {
-    typename C2<T>::type v = out[i * A.nrhs + r2];
+    CT v = out[i * A.nrhs + r2];
     v.x += accr[r2];
     v.y += acci[r2];
     out[i * A.nrhs + r2] = v;
@@ -481,26 +644,22 @@ prop_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc,
       y1 = x1 - S.center[3 * k + 1];
       y2 = x2 - S.center[3 * k + 2];
     }
-    ConeCoord c = cone_coord(S, hc, y0, y1, y2);
-    double u0, u1, u2;
-    int cs = cone_index(c.q[0], S.ns, u0);
-    int ct = cone_index(c.q[1], S.nt, u1);
-    int cp = cone_index(c.q[2], S.np, u2);
-    unsigned long long ckey = (unsigned long long)k * S.ngrid +
-                              ((unsigned long long)cs * S.nt + ct) * S.np + cp;
+    T u[3];
+    const ConeSel c = cone_select<T>(S, hc, y0, y1, y2, u);
+    const unsigned long long ckey = (unsigned long long)k * S.ngrid + (unsigned long long)c.gamma;
     int cslot = cone_lookup(S, ckey);
     if (cslot < 0) {
       miss = true;
       continue;
     }
     T Ls[PS], Lt[PA], Lp[PA];
-    lagrange<PS, T>((T)u0, A.cheb.ts, A.cheb.ws, Ls);
-    lagrange<PA, T>((T)u1, A.cheb.ta, A.cheb.wa, Lt);
-    lagrange<PA, T>((T)u2, A.cheb.ta, A.cheb.wa, Lp);
+    lagrange<PS, T>(u[0], A.cheb.ts, A.cheb.ws, Ls);
+    lagrange<PA, T>(u[1], A.cheb.ta, A.cheb.wa, Lt);
+    lagrange<PA, T>(u[2], A.cheb.ta, A.cheb.wa, Lp);
     // G(x, x_k) / G(x, x_j) = (r_j / r_k) e^{i kappa (r_k - r_j)}.
     T gc, gs;
     expi<T>(kappa * (c.r - rj), gc, gs);
-    T amp = (T)(rj / c.r);
+    T amp = (T)(rj * c.rinv);
     gc *= amp;
     gs *= amp;
     const typename C2<T>::type* vb = Vc + (int64_t)cslot * A.nrhs * P;
@@ -586,21 +745,18 @@ prop_node_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc
         y1 = x1 - S.center[3 * k + 1];
         y2 = x2 - S.center[3 * k + 2];
       }
-      ConeCoord c = cone_coord(S, hc, y0, y1, y2);
-      double u0, u1, u2;
-      const int cs = cone_index(c.q[0], S.ns, u0);
-      const int ct = cone_index(c.q[1], S.nt, u1);
-      const int cp = cone_index(c.q[2], S.np, u2);
-      const unsigned long long ckey = (unsigned long long)k * S.ngrid +
-                                      ((unsigned long long)cs * S.nt + ct) * S.np + cp;
+      T u[3];
+      const ConeSel c = cone_select<T>(S, hc, y0, y1, y2, u);
+      const unsigned long long ckey =
+          (unsigned long long)k * S.ngrid + (unsigned long long)c.gamma;
       cslot = cone_lookup(S, ckey);
       miss |= cslot < 0;
-      lagrange<PS, T>((T)u0, A.cheb.ts, A.cheb.ws, Ls);
-      lagrange<PA, T>((T)u1, A.cheb.ta, A.cheb.wa, Lt);
-      lagrange<PA, T>((T)u2, A.cheb.ta, A.cheb.wa, Lp);
+      lagrange<PS, T>(u[0], A.cheb.ts, A.cheb.ws, Ls);
+      lagrange<PA, T>(u[1], A.cheb.ta, A.cheb.wa, Lt);
+      lagrange<PA, T>(u[2], A.cheb.ta, A.cheb.wa, Lp);
       // G(x, x_k) / G(x, x_j) = (r_j / r_k) e^{i kappa (r_k - r_j)}.
       expi<T>(kappa * (c.r - rj), gc, gs);
-      const T amp = (T)(rj / c.r);
+      const T amp = (T)(rj * c.rinv);
       gc *= amp;
       gs *= amp;
     }
@@ -750,32 +906,14 @@ prop_mfma_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc
   // Node geometry, once per block.
   for (int i = tid; i < 8 * P; i += blockDim.x) {
     const int o = i / P, p = i - (i / P) * P;
-    const int a = p / (PA * PA), bb = (p / PA) % PA, cc = p % PA;
-    double yp[3];
-    node_offset<PS, PA>(Q, hp, is, it, ip, a, bb, cc, yp);
-    double y0, y1, y2, rj;
-    {
-      IFGF_NO_CONTRACT
-      // Child centre minus parent centre: (bit - 1/2) H_child per axis.
-      y0 = yp[0] - (((o >> 2) & 1) ? 0.5 * Hc : -0.5 * Hc);
-      y1 = yp[1] - (((o >> 1) & 1) ? 0.5 * Hc : -0.5 * Hc);
-      y2 = yp[2] - ((o & 1) ? 0.5 * Hc : -0.5 * Hc);
-      rj = sqrt(yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]);
-    }
-    ConeCoord cr = cone_coord(S, hc, y0, y1, y2);
-    double u0, u1, u2;
-    int cs = cone_index(cr.q[0], S.ns, u0);
-    int ct = cone_index(cr.q[1], S.nt, u1);
-    int cp = cone_index(cr.q[2], S.np, u2);
-    s_alpha[i] = (cs * S.nt + ct) * S.np + cp;
-    s_u[3 * i] = (T)u0;
-    s_u[3 * i + 1] = (T)u1;
-    s_u[3 * i + 2] = (T)u2;
-    T gc, gs;
-    expi<T>(kappa * (cr.r - rj), gc, gs);
-    T amp = (T)(rj / cr.r);
-    s_rat[2 * i] = gc * amp;
-    s_rat[2 * i + 1] = gs * amp;
+    T u[3];
+    typename C2<T>::type rat;
+    s_alpha[i] = node_octant_geometry<PS, PA, T>(S, Q, hp, hc, Hc, kappa, is, it, ip, o, p, u, rat);
+    s_u[3 * i] = u[0];
+    s_u[3 * i + 1] = u[1];
+    s_u[3 * i + 2] = u[2];
+    s_rat[2 * i] = rat.x;
+    s_rat[2 * i + 1] = rat.y;
   }
   __syncthreads();
   // Per octant (wave w: octants w and w + 4), the distinct child cones and
@@ -1253,31 +1391,14 @@ prop_big_kernel(ApplyArgs A, int l, const float2* __restrict__ Vc, float2* __res
   // Node geometry of (o, p), as in prop_mfma_kernel.
   for (int i = tid; i < 8 * P; i += blockDim.x) {
     const int o = i / P, p = i - (i / P) * P;
-    const int a = p / (PA * PA), bb = (p / PA) % PA, cc = p % PA;
-    double yp[3];
-    node_offset<PS, PA>(Q, hp, is, it, ip, a, bb, cc, yp);
-    double y0, y1, y2, rj;
-    {
-      IFGF_NO_CONTRACT
-      y0 = yp[0] - (((o >> 2) & 1) ? 0.5 * Hc : -0.5 * Hc);
-      y1 = yp[1] - (((o >> 1) & 1) ? 0.5 * Hc : -0.5 * Hc);
-      y2 = yp[2] - ((o & 1) ? 0.5 * Hc : -0.5 * Hc);
-      rj = sqrt(yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]);
-    }
-    ConeCoord cr = cone_coord(S, hc, y0, y1, y2);
-    double u0, u1, u2;
-    int cs = cone_index(cr.q[0], S.ns, u0);
-    int ct = cone_index(cr.q[1], S.nt, u1);
-    int cp = cone_index(cr.q[2], S.np, u2);
-    s_alpha[i] = (cs * S.nt + ct) * S.np + cp;
-    s_u[3 * i] = (float)u0;
-    s_u[3 * i + 1] = (float)u1;
-    s_u[3 * i + 2] = (float)u2;
-    float gcv, gsv;
-    expi<float>(kappa * (cr.r - rj), gcv, gsv);
-    const float amp = (float)(rj / cr.r);
-    s_ratp[2 * i] = gcv * amp;
-    s_ratp[2 * i + 1] = gsv * amp;
+    float u[3];
+    float2 rat;
+    s_alpha[i] = node_octant_geometry<PS, PA, float>(S, Q, hp, hc, Hc, kappa, is, it, ip, o, p, u, rat);
+    s_u[3 * i] = u[0];
+    s_u[3 * i + 1] = u[1];
+    s_u[3 * i + 2] = u[2];
+    s_ratp[2 * i] = rat.x;
+    s_ratp[2 * i + 1] = rat.y;
   }
   // Zero the W matrix once: its padding (nodes q >= P, k-steps >= NK) is
   // never written again.
@@ -1784,43 +1905,20 @@ struct OctRec {
   __device__ CT* ratg() const { return reinterpret_cast<CT*>(b + kRatg); }  // grouped order
 };
 
-// Node geometry of parent cone index (is, it, ip) of step l + 1 seen from
-// the child in octant o, for nodes p = t0, t0 + stride, ...: the child cone
-// alpha(p), the local coordinates u(p) and the ratio G(x_p, x_k)/G(x_p, x_j)
-// (phase reduced in FP64).
+// node_octant_geometry for nodes p = t0, t0 + stride, ... into a record.
 template <int PS, int PA, typename T>
 __device__ __forceinline__ void octant_geometry(const StepDev& S, const StepDev& Q, double hp,
                                                 double hc, double Hc, double kappa, int is,
                                                 int it, int ip, int o, int t0, int stride,
                                                 int* s_alpha, OctRec<PS * PA * PA, T> R) {
-  typedef typename C2<T>::type CT;
   constexpr int P = PS * PA * PA;
   for (int p = t0; p < P; p += stride) {
-    const int a = p / (PA * PA), bb = (p / PA) % PA, cc = p % PA;
-    double yp[3];
-    node_offset<PS, PA>(Q, hp, is, it, ip, a, bb, cc, yp);
-    double y0, y1, y2, rj;
-    {
-      IFGF_NO_CONTRACT
-      y0 = yp[0] - (((o >> 2) & 1) ? 0.5 * Hc : -0.5 * Hc);
-      y1 = yp[1] - (((o >> 1) & 1) ? 0.5 * Hc : -0.5 * Hc);
-      y2 = yp[2] - ((o & 1) ? 0.5 * Hc : -0.5 * Hc);
-      rj = sqrt(yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]);
-    }
-    ConeCoord cr = cone_coord(S, hc, y0, y1, y2);
-    double u0, u1, u2;
-    const int cs = cone_index(cr.q[0], S.ns, u0);
-    const int ct = cone_index(cr.q[1], S.nt, u1);
-    const int cp = cone_index(cr.q[2], S.np, u2);
-    s_alpha[p] = (cs * S.nt + ct) * S.np + cp;
-    T* u = R.u();
-    u[3 * p] = (T)u0;
-    u[3 * p + 1] = (T)u1;
-    u[3 * p + 2] = (T)u2;
-    T gcv, gsv;
-    expi<T>(kappa * (cr.r - rj), gcv, gsv);
-    const T amp = (T)(rj / cr.r);
-    R.ratp()[p] = CT{gcv * amp, gsv * amp};
+    T u[3];
+    s_alpha[p] = node_octant_geometry<PS, PA, T>(S, Q, hp, hc, Hc, kappa, is, it, ip, o, p, u,
+                                                 R.ratp()[p]);
+    R.u()[3 * p] = u[0];
+    R.u()[3 * p + 1] = u[1];
+    R.u()[3 * p + 2] = u[2];
   }
 }
 
@@ -2452,8 +2550,8 @@ static hipError_t apply_impl(const ApplyArgs& A, const void* dens_user,
                      <<<nblk(S0.ncones * P, 256), 256, 0, st>>>(A, Vcur)));
     for (int l = 0; l < A.n_steps; ++l) {
       if (A.step_host[l].ncones > 0)
-        IFGF_TIMED(3, (interp_kernel<PS, PA, T, MAXR>
-                       <<<nblk(A.n, 256), 256, 0, st>>>(A, l, Vcur, os)));
+        IFGF_TIMED(3, (interp_kernel<PS, PA, T, MAXR><<<nblk(A.n, 64), 64 * kInterpParts, 0,
+                                                        st>>>(A, l, Vcur, os)));
       if (l + 1 < A.n_steps && A.step_host[l + 1].ncones > 0) {
         const StepDev& Qh = A.step_host[l + 1];
         bool done = false;
