@@ -365,6 +365,20 @@ static void build_device(ifgf_plan_s* P) {
   A.y = P->upload(m.xs[1]);
   A.z = P->upload(m.xs[2]);
   A.perm = P->upload(m.perm);
+  // Leaf-box-relative FP32 source offsets for LevelDEvaluations.
+  A.q_leaf = nullptr;
+  if (P->opts.precision != IFGF_FP64 && L > 0) {
+    const MergedStep& S0 = m.step[0];
+    std::vector<float4> q((size_t)m.n, float4{0.f, 0.f, 0.f, 0.f});
+    for (int64_t b = 0; b < S0.nb; ++b)
+      for (int64_t i = S0.first[b]; i < (int64_t)S0.first[b] + S0.count[b]; ++i) {
+        const float q0 = (float)(m.xs[0][i] - S0.center[3 * b]);
+        const float q1 = (float)(m.xs[1][i] - S0.center[3 * b + 1]);
+        const float q2 = (float)(m.xs[2][i] - S0.center[3 * b + 2]);
+        q[i] = float4{q0, q1, q2, q0 * q0 + q1 * q1 + q2 * q2};
+      }
+    A.q_leaf = P->upload(q);
+  }
   A.inst_kappa = P->upload(m.inst_kappa);
   A.nbr_begin = P->upload(m.nbr_begin);
   A.nbr = P->upload(m.nbr);

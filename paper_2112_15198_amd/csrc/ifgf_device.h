@@ -108,6 +108,8 @@ struct ApplyArgs {
   const double* x;            // sorted coordinates
   const double* y;
   const double* z;
+  const float4* q_leaf;       // FP32 modes: per sorted point (x - c, |x - c|^2),
+                              // c the centre of its leaf box; null in FP64 mode
   const int* perm;            // sorted index -> caller index
   const double* inst_kappa;
   const int64_t* nbr_begin;   // level-D neighbour CSR
