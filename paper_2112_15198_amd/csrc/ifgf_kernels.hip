@@ -1879,6 +1879,85 @@ __device__ __forceinline__ void small_tile(const T* s_L, const T* s_u, const Che
   }
 }
 
+// One M-tile of the one-wave kernel against its (one or two) N-tiles of
+// complex-interleaved columns: the Lagrange factors of the lane's row are
+// evaluated once, the two products run as interleaved accumulation chains,
+// and each N-tile's partner lanes complete the complex ratio multiply as in
+// small_tile.
+template <int PS, int PA, typename T, int MAXR>
+__device__ __forceinline__ void small_tile_cplx2(const T* s_u, const ChebConst& cheb, T wak,
+                                                 T wbk, const typename C2<T>::type* s_ratp,
+                                                 const unsigned char* s_rows,
+                                                 typename C2<T>::type* y, int rb, int rlen,
+                                                 int ntn, const int* yb, const bool* colok,
+                                                 int lane, int part, const T* br0,
+                                                 const T* br1) {
+  typedef SmallProp<PS, PA, T, MAXR> SP;
+  typedef typename C2<T>::type CT;
+  typedef typename Mfma<T>::v4 V4;
+  constexpr int P = SP::P, NG = SP::NG;
+  const int kq = lane >> 4;
+  const int arow = min(rb + (lane & 15), P - 1);
+  T ab[NG], Lc[PA];
+  {
+    T La[PS], Lb4[PA > 4 ? PA - 4 : 1];
+    const T* u = s_u + 3 * (int)s_rows[arow];
+    const T u0 = u[0], u1 = u[1];
+    lagrange<PS, T>(u0, cheb.ts, cheb.ws, La);
+    lagrange<PA, T>(u[2], cheb.ta, cheb.wa, Lc);
+    const T lak = kq < PS ? lagrange_at<PS, T>(u0, cheb.ts, kq, wak) : (T)0;
+    const T lbk = kq < SP::PB ? lagrange_at<PA, T>(u1, cheb.ta, kq, wbk) : (T)0;
+#pragma unroll
+    for (int e = 0; e < SP::NE; ++e)
+      Lb4[e] = lagrange_at<PA, T>(u1, cheb.ta, 4 + e, (T)cheb.wa[4 + e]);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) ab[g] = g < PS ? La[g] * lbk : lak * Lb4[g < PS ? 0 : g - PS];
+  }
+  int pe[4];
+  CT rat[4];
+#pragma unroll
+  for (int r4 = 0; r4 < 4; ++r4) {
+    const int mm = Mfma<T>::row(lane, r4);
+    pe[r4] = mm < rlen ? (int)s_rows[rb + mm] : -1;
+    rat[r4] = s_ratp[pe[r4] >= 0 ? pe[r4] : 0];
+  }
+  V4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+  if (ntn > 1) {
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+      for (int c = 0; c < PA; ++c) {
+        const T av = ab[g] * Lc[c];
+        acc0 = Mfma<T>::mma(av, br0[g * PA + c], acc0);
+        acc1 = Mfma<T>::mma(av, br1[g * PA + c], acc1);
+      }
+  } else {
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+      for (int c = 0; c < PA; ++c) acc0 = Mfma<T>::mma(ab[g] * Lc[c], br0[g * PA + c], acc0);
+  }
+  T* yf = reinterpret_cast<T*>(y);
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    if (t >= ntn) break;  // uniform
+    const V4 acc = t ? acc1 : acc0;
+    T oth[4];
+#pragma unroll
+    for (int r4 = 0; r4 < 4; ++r4) oth[r4] = __shfl_xor(acc[r4], 1);
+    if (colok[t]) {
+#pragma unroll
+      for (int r4 = 0; r4 < 4; ++r4) {
+        if (pe[r4] >= 0) {
+          const T re = part ? oth[r4] : acc[r4], im = part ? acc[r4] : oth[r4];
+          const T v = part ? re * rat[r4].y + im * rat[r4].x : re * rat[r4].x - im * rat[r4].y;
+          yf[2 * (yb[t] + pe[r4]) + part] += v;
+        }
+      }
+    }
+  }
+}
+
 // Box-independent data of one (parent cone index gamma', octant o) of a
 // propagation step, in one record (the same layout in LDS and in the
 // plan-time table): the number of distinct child cones na and of M-tiles
@@ -2165,58 +2244,97 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
       }
     }
     __syncthreads();
-    // Work items (N-tile nt, M-tile j), nt major; wave w takes a contiguous
-    // range and walks it unit by unit, a unit being the M-tiles of one
-    // (nt, child cone k) in the range, with one B load per unit.
     const int ncols = no * nrhs;  // complex columns (child, rhs)
-    const int nit = (CPLX ? (ncols + 7) >> 3 : (ncols + 15) >> 4) * nm;
-    const int i0 = (int)(((int64_t)nit * wave) / NWV), i1 = (int)(((int64_t)nit * (wave + 1)) / NWV);
-    int nt = i0 / nm, k = 0, rb = 0, rend = 0;
-    if (i0 < i1) {
-      if constexpr (NWV > 1) {
-        const int j = i0 - nt * nm;
-        k = s_mk[j];
-        rb = s_mr[j];
+    if constexpr (NWV == 1 && !SPLIT) {
+      // One wave: at most 16 complex columns (a box has one child per
+      // octant), so at most two N-tiles.  Per child cone the B values of
+      // both are loaded once, and each M-tile's factors serve both.
+      const int ntn = (ncols + 7) >> 3;
+      int n0c[2], rc[2], ybc[2];
+      bool okc[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int c = t * 8 + (col >> 1);
+        okc[t] = c < ncols;
+        n0c[t] = !okc[t] ? 0 : MAXR == 1 ? c : c / nrhs;
+        rc[t] = !okc[t] || MAXR == 1 ? 0 : c - n0c[t] * nrhs;
+        ybc[t] = okc[t] ? ((int)s_nl[o][n0c[t]] * MAXR + rc[t]) * P : 0;
       }
-      rend = s_rbeg[k + 1];
-    }
-    int item = i0;
-    while (item < i1) {
-      const int part = CPLX ? col & 1 : 0;
-      const int c = CPLX ? nt * 8 + (col >> 1) : nt * 16 + col;
-      const bool colok = c < ncols;
-      const int n0 = !colok ? 0 : MAXR == 1 ? c : c / nrhs;
-      const int r = !colok || MAXR == 1 ? 0 : c - n0 * nrhs;
-      const int yb = colok ? ((int)s_nl[o][n0] * MAXR + r) * P : 0;
-      int cs;
-      if (k < NAMAX) {
-        cs = s_cs[n0 * NAMAX + k];
-      } else {
-        cs = cone_lookup(S, (unsigned long long)s_ch[o][n0] * S.ngrid + s_dist[k]);
-        miss |= cs < 0;
-      }
-      T br[SP::NK], bi[CPLX ? 1 : SP::NK];
-      const CT* vsrc = Vc + ((int64_t)(cs >= 0 ? cs : 0) * nrhs + r) * P;
-      if constexpr (CPLX)
-        small_load_b1<PS, PA, T, MAXR>(vsrc, kq, part, br);
-      else
-        small_load_b<PS, PA, T, MAXR>(vsrc, kq, br, bi);
-      SplitB<SP::NK> sb;
-      if constexpr (SPLIT) split_b<SP::NK>((const float*)br, (const float*)(CPLX ? br : bi), sb);
-      do {
-        small_tile<PS, PA, T, MAXR, LREG, SPLIT, CPLX>(s_L, s_u, A.cheb, wak, wbk, s_ratp, s_rows,
-                                                       s_y, rb, min(16, rend - rb), yb, colok,
-                                                       lane, part, br, bi, sb);
-        ++item;
-        rb += 16;
-      } while (item < i1 && rb < rend);
-      if (rb >= rend) {  // next child cone, or the first of the next N-tile
-        if (++k == na) {
-          k = 0;
-          ++nt;
+      const int part = col & 1;
+      for (int k = 0; k < na; ++k) {
+        T b0[SP::NK], b1[SP::NK];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          if (t < ntn) {
+            int cs;
+            if (k < NAMAX) {
+              cs = s_cs[n0c[t] * NAMAX + k];
+            } else {
+              cs = cone_lookup(S, (unsigned long long)s_ch[o][n0c[t]] * S.ngrid + s_dist[k]);
+              miss |= cs < 0;
+            }
+            const CT* vsrc = Vc + ((int64_t)(cs >= 0 ? cs : 0) * nrhs + rc[t]) * P;
+            small_load_b1<PS, PA, T, MAXR>(vsrc, kq, part, t ? b1 : b0);
+          }
         }
-        rb = s_rbeg[k];
+        for (int rb = s_rbeg[k]; rb < s_rbeg[k + 1]; rb += 16)
+          small_tile_cplx2<PS, PA, T, MAXR>(s_u, A.cheb, wak, wbk, s_ratp, s_rows, s_y, rb,
+                                            min(16, s_rbeg[k + 1] - rb), ntn, ybc, okc, lane,
+                                            part, b0, b1);
+      }
+    } else {
+      // Work items (N-tile nt, M-tile j), nt major; wave w takes a contiguous
+      // range and walks it unit by unit, a unit being the M-tiles of one
+      // (nt, child cone k) in the range, with one B load per unit.
+      const int nit = (CPLX ? (ncols + 7) >> 3 : (ncols + 15) >> 4) * nm;
+      const int i0 = (int)(((int64_t)nit * wave) / NWV), i1 = (int)(((int64_t)nit * (wave + 1)) / NWV);
+      int nt = i0 / nm, k = 0, rb = 0, rend = 0;
+      if (i0 < i1) {
+        if constexpr (NWV > 1) {
+          const int j = i0 - nt * nm;
+          k = s_mk[j];
+          rb = s_mr[j];
+        }
         rend = s_rbeg[k + 1];
+      }
+      int item = i0;
+      while (item < i1) {
+        const int part = CPLX ? col & 1 : 0;
+        const int c = CPLX ? nt * 8 + (col >> 1) : nt * 16 + col;
+        const bool colok = c < ncols;
+        const int n0 = !colok ? 0 : MAXR == 1 ? c : c / nrhs;
+        const int r = !colok || MAXR == 1 ? 0 : c - n0 * nrhs;
+        const int yb = colok ? ((int)s_nl[o][n0] * MAXR + r) * P : 0;
+        int cs;
+        if (k < NAMAX) {
+          cs = s_cs[n0 * NAMAX + k];
+        } else {
+          cs = cone_lookup(S, (unsigned long long)s_ch[o][n0] * S.ngrid + s_dist[k]);
+          miss |= cs < 0;
+        }
+        T br[SP::NK], bi[CPLX ? 1 : SP::NK];
+        const CT* vsrc = Vc + ((int64_t)(cs >= 0 ? cs : 0) * nrhs + r) * P;
+        if constexpr (CPLX)
+          small_load_b1<PS, PA, T, MAXR>(vsrc, kq, part, br);
+        else
+          small_load_b<PS, PA, T, MAXR>(vsrc, kq, br, bi);
+        SplitB<SP::NK> sb;
+        if constexpr (SPLIT) split_b<SP::NK>((const float*)br, (const float*)(CPLX ? br : bi), sb);
+        do {
+          small_tile<PS, PA, T, MAXR, LREG, SPLIT, CPLX>(s_L, s_u, A.cheb, wak, wbk, s_ratp, s_rows,
+                                                         s_y, rb, min(16, rend - rb), yb, colok,
+                                                         lane, part, br, bi, sb);
+          ++item;
+          rb += 16;
+        } while (item < i1 && rb < rend);
+        if (rb >= rend) {  // next child cone, or the first of the next N-tile
+          if (++k == na) {
+            k = 0;
+            ++nt;
+          }
+          rb = s_rbeg[k];
+          rend = s_rbeg[k + 1];
+        }
       }
     }
     __syncthreads();
