@@ -9,7 +9,7 @@
 //                        interpolation nodes of every relevant leaf cone.
 //   interp_kernel        Interpolation(d): per target, sum over its cousin
 //                        boxes of I_P C(x) * G(x, x_k).
-//   prop_kernel          Propagation(d): per relevant parent cone node x,
+//   prop_*_kernel        Propagation(d): per relevant parent cone node x,
 //                        sum over relevant children of I_P C_k(x) *
 //                        G(x,x_k)/G(x,x_j).
 // Plan-time kernels build the relevant cone segments
@@ -599,91 +599,6 @@ interp_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V,
     v.x += accr[r2];
     v.y += acci[r2];
     out[i * A.nrhs + r2] = v;
-  }
-}
-
-// Propagation from step l (level d) to step l+1 (level d-1): one thread per
-// (relevant parent cone, node p).
-template <int PS, int PA, typename T, int MAXR>
-__global__ void __launch_bounds__(256)
-prop_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc,
-            typename C2<T>::type* __restrict__ Vp) {
-  constexpr int P = PS * PA * PA;
-  const StepDev& S = A.step[l];
-  const StepDev& Q = A.step[l + 1];
-  int64_t t = gtid();
-  if (t >= Q.ncones * P) return;
-  int64_t slot = t / P;
-  int p = (int)(t - slot * P);
-  unsigned long long key = Q.cone_key[slot];
-  int64_t j = (int64_t)(key / (unsigned long long)Q.ngrid);
-  int64_t g = (int64_t)(key - (unsigned long long)j * Q.ngrid);
-  int is = (int)(g / ((int64_t)Q.nt * Q.np));
-  int it = (int)((g / Q.np) % Q.nt);
-  int ip = (int)(g % Q.np);
-  int a = p / (PA * PA), bb = (p / PA) % PA, cc = p % PA;
-  int inst = Q.inst[j];
-  double hp = Q.inst_h[inst];
-  double hc = S.inst_h[inst];
-  double kappa = A.inst_kappa[inst];
-  double cjx = Q.center[3 * j], cjy = Q.center[3 * j + 1], cjz = Q.center[3 * j + 2];
-  double yp[3];
-  node_offset<PS, PA>(Q, hp, is, it, ip, a, bb, cc, yp);
-  double x0, x1, x2, rj;
-  {
-    IFGF_NO_CONTRACT
-    x0 = cjx + yp[0];
-    x1 = cjy + yp[1];
-    x2 = cjz + yp[2];
-    double e0 = x0 - cjx, e1 = x1 - cjy, e2 = x2 - cjz;
-    rj = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
-  }
-  T accr[MAXR], acci[MAXR];
-#pragma unroll
-  for (int r = 0; r < MAXR; ++r) accr[r] = acci[r] = 0;
-  bool miss = false;  // a cone look-up missed (reported once, after the loop)
-  for (int o = 0; o < 8; ++o) {
-    int k = Q.child[8 * j + o];
-    if (k < 0) continue;
-    double y0, y1, y2;
-    {
-      IFGF_NO_CONTRACT
-      y0 = x0 - S.center[3 * k];
-      y1 = x1 - S.center[3 * k + 1];
-      y2 = x2 - S.center[3 * k + 2];
-    }
-    T u[3];
-    const ConeSel c = cone_select<T>(S, hc, y0, y1, y2, u);
-    const unsigned long long ckey = (unsigned long long)k * S.ngrid + (unsigned long long)c.gamma;
-    int cslot = cone_lookup(S, ckey);
-    if (cslot < 0) {
-      miss = true;
-      continue;
-    }
-    T Ls[PS], Lt[PA], Lp[PA];
-    lagrange<PS, T>(u[0], A.cheb.ts, A.cheb.ws, Ls);
-    lagrange<PA, T>(u[1], A.cheb.ta, A.cheb.wa, Lt);
-    lagrange<PA, T>(u[2], A.cheb.ta, A.cheb.wa, Lp);
-    // G(x, x_k) / G(x, x_j) = (r_j / r_k) e^{i kappa (r_k - r_j)}.
-    T gc, gs;
-    expi<T>(kappa * (c.r - rj), gc, gs);
-    T amp = (T)(rj * c.rinv);
-    gc *= amp;
-    gs *= amp;
-    const typename C2<T>::type* vb = Vc + (int64_t)cslot * A.nrhs * P;
-    for (int r2 = 0; r2 < A.nrhs && r2 < MAXR; ++r2) {
-      T vr, vi;
-      contract<PS, PA, T>(vb + r2 * P, Ls, Lt, Lp, vr, vi);
-      accr[r2] += vr * gc - vi * gs;
-      acci[r2] += vr * gs + vi * gc;
-    }
-  }
-  if (miss) atomicOr(A.err, 1);
-  for (int r2 = 0; r2 < A.nrhs && r2 < MAXR; ++r2) {
-    typename C2<T>::type v;
-    v.x = accr[r2];
-    v.y = acci[r2];
-    Vp[(slot * A.nrhs + r2) * P + p] = v;
   }
 }
 
@@ -2630,17 +2545,13 @@ int chunk_boxes(int precision, int nrhs) {
 // The grouped (matrix-core) propagation of one level: 512-thread blocks in
 // FP32, 256-thread blocks in FP64 (whose operands do not fit the former's
 // LDS layout).
-// The per-node propagation: the LDS-staged kernel (IFGF_NODE_GLOBAL selects
-// the plain per-node kernel, which reads every value from global memory).
+// The per-node propagation: one thread per (relevant parent cone, node),
+// child cones staged in LDS per wave.
 template <int PS, int PA, typename T, int MAXR>
 static void launch_prop_node(const ApplyArgs& A, int l, const typename C2<T>::type* Vc,
                              typename C2<T>::type* Vp, int64_t ncones, hipStream_t st) {
   constexpr int P = PS * PA * PA;
-#ifdef IFGF_NODE_GLOBAL
-  prop_kernel<PS, PA, T, MAXR><<<nblk(ncones * P, 256), 256, 0, st>>>(A, l, Vc, Vp);
-#else
   prop_node_kernel<PS, PA, T, MAXR><<<nblk(ncones * P, 64), 64, 0, st>>>(A, l, Vc, Vp);
-#endif
 }
 
 template <int PS, int PA, typename T, int MAXR>
