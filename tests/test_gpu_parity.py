@@ -140,6 +140,39 @@ def test_fp32_paper_spheroids(geom):
     assert relerr(g[0], d) <= 1e-3
 
 
+@pytest.mark.parametrize("prop", ["node", "small", "medium"])
+@pytest.mark.parametrize("case", ["wide", "odd", "deep", "clusters", "bigleaf"])
+def test_fp32_cone_selection_matches_oracle(case, prop):
+    """FP32-mixed propagation picks each angle's cone from an FP32 estimate
+    confirmed with FP64 side tests against the cone boundaries, and the leaf
+    evaluation reduces its phase turns in FP32.  Cases that stress both: the
+    widest cones (leaf grid (1,2,4): theta and phi widths pi/2), odd cone
+    counts ((3,3,5)), a forced deep tree (narrow cones at the top), clustered
+    points, and leaves of a wavelength (four times the default side).  The
+    per-node, one-wave and four-wave forms against the oracle IFGF at the
+    FP32 bar, 2e-5, element-wise and in l2."""
+    grid, lv, size = (2, 4, 8), 0, 0.25
+    if case == "wide":
+        p, k, grid = W.fibonacci_sphere(3000), W.kappa_sphere_10ppw(3000), (1, 2, 4)
+    elif case == "odd":
+        p, k, grid = W.fibonacci_sphere(3000), W.kappa_sphere_10ppw(3000), (3, 3, 5)
+    elif case == "deep":
+        p, k, lv = W.fibonacci_sphere(2500), 10.0, 6
+    elif case == "clusters":
+        rng = np.random.default_rng(3)
+        p = np.vstack([rng.normal(size=(1500, 3)) * 0.05 - [1.0, 0, 0],
+                       rng.normal(size=(1500, 3)) * 0.05 + [1.0, 0.3, 0]])
+        k = 12.0
+    else:  # 2.5 points per wavelength: leaf boxes of about a wavelength, D = 5
+        p, k, size = W.fibonacci_sphere(6000), 4.0 * W.kappa_sphere_10ppw(6000), 1.0
+    a = W.densities(len(p), 1, 52)
+    say("fp32 cone selection", case, prop, "N=", len(p), "grid", grid, "levels", lv)
+    g, _ = run_gpu(p, a, k, precision="fp32", prop_kernel=prop, leaf_grid=grid, levels=lv,
+                   leaf_size=size)
+    o = oracle.ifgf(p, a[0], k, leaf_grid=grid, levels=lv, leaf_size=size)
+    assert_close(g[0], o, 2e-5, f"fp32 {case} {prop}")
+
+
 @pytest.mark.parametrize("ps,pa", [(2, 3), (5, 7)])
 def test_other_orders_match_oracle(ps, pa):
     n = 3000
