@@ -482,20 +482,22 @@ leaf_eval_kernel(ApplyArgs A, typename C2<T>::type* __restrict__ V) {
     // |q|^2); the phase |y - q| - |y| = (|q|^2 - 2 y.q) / (|y - q| + |y|) has
     // no cancellation and is at most the box diameter, so its number of
     // turns is reduced in FP32 and e^{i kappa diff} taken from the hardware
-    // sine and cosine.  Quotients by the hardware reciprocal (1 ulp).
+    // sine and cosine.  Quotients by the hardware reciprocal and reciprocal
+    // square root (1 ulp).
     const float y0 = (float)y[0], y1 = (float)y[1], y2 = (float)y[2];
     const float ry = sqrtf(y0 * y0 + y1 * y1 + y2 * y2);
     const float kturn = (float)(kappa * kInv2Pi);
     for (int m = m0; m < m1; ++m) {
       const float4 q = A.q_leaf[m];
       const float d0 = y0 - q.x, d1 = y1 - q.y, d2 = y2 - q.z;
-      const float r = __builtin_amdgcn_sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+      const float r2 = d0 * d0 + d1 * d1 + d2 * d2;
+      const float rinv = __builtin_amdgcn_rsqf(r2);  // 1/|y - q|, and |y - q| = r2 / it
       const float diff =
-          (q.w - 2.0f * (y0 * q.x + y1 * q.y + y2 * q.z)) * __builtin_amdgcn_rcpf(r + ry);
+          (q.w - 2.0f * (y0 * q.x + y1 * q.y + y2 * q.z)) * __builtin_amdgcn_rcpf(r2 * rinv + ry);
       const float turns = kturn * diff;
       const float f = turns - rintf(turns);
       float sn = __builtin_amdgcn_sinf(f), cs = __builtin_amdgcn_cosf(f);
-      const float amp = ry * __builtin_amdgcn_rcpf(r);
+      const float amp = ry * rinv;
       cs *= amp;
       sn *= amp;
       for (int r2 = 0; r2 < A.nrhs && r2 < MAXR; ++r2) {
