@@ -159,7 +159,10 @@ typedef struct ifgf_info {
                                          5 four-wave tasks, smaller chunks */
   float autotune_ms[IFGF_MAX_LEVELS][5]; /* autotuner timings of Propagation
                                          into step l, kernels 1..5 in order
-                                         (0 when not tuned) */
+                                         (0 when not tuned): the mean of two
+                                         launches, or one launch for a form
+                                         whose first launch took 1.5 times
+                                         the best so far */
   int64_t leaf_pairs;     /* (leaf-cone node, source) evaluations of
                              LevelDEvaluations */
   int64_t near_pairs;     /* (target, source) near-field pairs, self included */

@@ -286,17 +286,31 @@ static void autotune(ifgf_plan_s* P) {
   for (int l = 0; l + 1 < A.n_steps; ++l) {
     StepDev& Q = P->steps_h[l + 1];
     if (Q.ncones == 0 || Q.nchunks == 0) continue;
+    // Each form: a timed warm-up launch, then two timed launches, unless the
+    // warm-up alone is 1.5 times the best so far (then it stands for the form;
+    // the slow forms of a level cost one launch).  The rule-based choice goes
+    // first, so that the others are measured against a good form.
     float best[kPropKinds] = {0, 0, 0, 0, 0};
-    int pick = kPropNode;
-    for (int g = kPropNode; g < kPropKinds; ++g) {
+    int pick = -1;
+    for (int q = 0; q < kPropKinds; ++q) {
+      const int g = q == 0 ? Q.prop_grouped : (q <= Q.prop_grouped ? q - 1 : q);
+      float warm = 0;
+      HIP_TRY(hipEventRecord(e0, st));
       HIP_TRY(launch_prop_level(A, l, P->p_s, P->p_ang, P->opts.precision, g, st));
+      HIP_TRY(hipEventRecord(e1, st));
+      HIP_TRY(hipEventSynchronize(e1));
+      HIP_TRY(hipEventElapsedTime(&warm, e0, e1));
+      if (pick >= 0 && warm > 1.5f * best[pick] / 2) {
+        best[g] = 2 * warm;
+        continue;
+      }
       HIP_TRY(hipEventRecord(e0, st));
       for (int rep = 0; rep < 2; ++rep)
         HIP_TRY(launch_prop_level(A, l, P->p_s, P->p_ang, P->opts.precision, g, st));
       HIP_TRY(hipEventRecord(e1, st));
       HIP_TRY(hipEventSynchronize(e1));
       HIP_TRY(hipEventElapsedTime(&best[g], e0, e1));
-      if (best[g] < best[pick]) pick = g;
+      if (pick < 0 || best[g] < best[pick]) pick = g;
     }
     Q.prop_grouped = pick;
     for (int g = 0; g < kPropKinds; ++g) P->info.autotune_ms[l + 1][g] = best[g] / 2;
@@ -540,16 +554,18 @@ static void build_device(ifgf_plan_s* P) {
       D.prop_table = nullptr;
       if (l >= 1 && count > 0) {
         const uint64_t ng = (uint64_t)D.ngrid;
+        // Slots sorted by (instance, gamma, slot): the composite key
+        // instance * grid + gamma is formed once per cone (a comparator that
+        // divides by the grid size made this sort most of the plan time at
+        // a million points and more).
+        std::vector<std::pair<uint64_t, int32_t>> sk((size_t)count);
+        for (int64_t i = 0; i < (int64_t)count; ++i) {
+          const uint64_t b = hkeys[i] / ng;
+          sk[i] = {(uint64_t)S.inst[b] * ng + (hkeys[i] - b * ng), (int32_t)i};
+        }
+        std::sort(sk.begin(), sk.end());
         std::vector<int32_t> order(count);
-        for (int64_t i = 0; i < (int64_t)count; ++i) order[i] = (int32_t)i;
-        auto gk = [&](int32_t i) {
-          uint64_t b = hkeys[i] / ng;
-          return std::make_pair(S.inst[b], hkeys[i] - b * ng);
-        };
-        std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
-          auto a = gk(x), b = gk(y);
-          return a != b ? a < b : x < y;
-        });
+        for (int64_t i = 0; i < (int64_t)count; ++i) order[i] = sk[i].second;
         // Chunks of at most cbox (block kernel) and sbox (one-wave kernel)
         // boxes sharing (instance, gamma).
         const int cbox = chunk_boxes(P->opts.precision, P->opts.n_rhs);
@@ -560,7 +576,7 @@ static void build_device(ifgf_plan_s* P) {
         std::vector<int32_t> clen, slen, mlen, llen, sgroup, mgroup, lgroup;
         int64_t groups = 0;
         for (int64_t i = 0; i < (int64_t)count; ++i) {
-          bool same = i > 0 && gk(order[i]) == gk(order[i - 1]);
+          bool same = i > 0 && sk[i].first == sk[i - 1].first;
           if (!same) {
             ++groups;
             gfirst.push_back(i);
