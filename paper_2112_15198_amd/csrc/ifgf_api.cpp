@@ -555,17 +555,33 @@ static void build_device(ifgf_plan_s* P) {
       if (l >= 1 && count > 0) {
         const uint64_t ng = (uint64_t)D.ngrid;
         // Slots sorted by (instance, gamma, slot): the composite key
-        // instance * grid + gamma is formed once per cone (a comparator that
-        // divides by the grid size made this sort most of the plan time at
-        // a million points and more).
-        std::vector<std::pair<uint64_t, int32_t>> sk((size_t)count);
-        for (int64_t i = 0; i < (int64_t)count; ++i) {
-          const uint64_t b = hkeys[i] / ng;
-          sk[i] = {(uint64_t)S.inst[b] * ng + (hkeys[i] - b * ng), (int32_t)i};
+        // instance * grid + gamma of every cone, radix-sorted on the device
+        // with the slot as value (stable, so equal keys stay in slot order;
+        // a host sort was most of the plan time at a million points).
+        std::vector<uint64_t> gkey((size_t)count);
+        std::vector<int32_t> order((size_t)count);
+        {
+          unsigned long long* gk = P->dalloc<unsigned long long>((int64_t)count);
+          unsigned long long* gk2 = P->dalloc<unsigned long long>((int64_t)count);
+          int* ix = P->dalloc<int>((int64_t)count);
+          int* ix2 = P->dalloc<int>((int64_t)count);
+          HIP_TRY(launch_group_keys(keys, (int64_t)count, ng, D.inst, gk, ix, st));
+          const int gbits = bits_for((uint64_t)m.n_inst * ng);
+          size_t sbytes = 0;
+          HIP_TRY(sort_pairs(gk, gk2, ix, ix2, (int64_t)count, gbits, nullptr, &sbytes, st));
+          void* scratch = P->dalloc<char>((int64_t)sbytes + 16);
+          HIP_TRY(sort_pairs(gk, gk2, ix, ix2, (int64_t)count, gbits, scratch, &sbytes, st));
+          HIP_TRY(hipMemcpyAsync(gkey.data(), gk2, sizeof(uint64_t) * count,
+                                 hipMemcpyDeviceToHost, st));
+          HIP_TRY(hipMemcpyAsync(order.data(), ix2, sizeof(int32_t) * count,
+                                 hipMemcpyDeviceToHost, st));
+          HIP_TRY(hipStreamSynchronize(st));
+          P->dfree(scratch);
+          P->dfree(ix2);
+          P->dfree(ix);
+          P->dfree(gk2);
+          P->dfree(gk);
         }
-        std::sort(sk.begin(), sk.end());
-        std::vector<int32_t> order(count);
-        for (int64_t i = 0; i < (int64_t)count; ++i) order[i] = sk[i].second;
         // Chunks of at most cbox (block kernel) and sbox (one-wave kernel)
         // boxes sharing (instance, gamma).
         const int cbox = chunk_boxes(P->opts.precision, P->opts.n_rhs);
@@ -576,7 +592,7 @@ static void build_device(ifgf_plan_s* P) {
         std::vector<int32_t> clen, slen, mlen, llen, sgroup, mgroup, lgroup;
         int64_t groups = 0;
         for (int64_t i = 0; i < (int64_t)count; ++i) {
-          bool same = i > 0 && sk[i].first == sk[i - 1].first;
+          bool same = i > 0 && gkey[i] == gkey[i - 1];
           if (!same) {
             ++groups;
             gfirst.push_back(i);

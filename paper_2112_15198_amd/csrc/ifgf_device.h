@@ -161,6 +161,12 @@ hipError_t launch_build_lookup(const unsigned long long* keys, int64_t n,
                                unsigned long long* tab, int* val,
                                unsigned long long mask, int* overflow,
                                hipStream_t st);
+hipError_t launch_group_keys(const unsigned long long* keys, int64_t n, unsigned long long ng,
+                             const int* inst, unsigned long long* gk, int* idx,
+                             hipStream_t st);
+hipError_t sort_pairs(const unsigned long long* keys_in, unsigned long long* keys_out,
+                      const int* vals_in, int* vals_out, int64_t n, int end_bit, void* scratch,
+                      size_t* scratch_bytes, hipStream_t st);
 hipError_t sort_keys(unsigned long long* keys, unsigned long long* tmp,
                      int64_t n, int end_bit, void* scratch,
                      size_t* scratch_bytes, hipStream_t st);

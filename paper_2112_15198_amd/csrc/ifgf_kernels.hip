@@ -2523,6 +2523,36 @@ hipError_t launch_build_lookup(const unsigned long long* keys, int64_t n,
   return hipGetLastError();
 }
 
+// Group keys of a level's cones: instance * grid + gamma, with the slot as
+// the value to sort.
+__global__ void group_key_kernel(const unsigned long long* __restrict__ keys, int64_t n,
+                                 unsigned long long ng, const int* __restrict__ inst,
+                                 unsigned long long* __restrict__ gk, int* __restrict__ idx) {
+  const int64_t t = gtid();
+  if (t >= n) return;
+  const unsigned long long k = keys[t], b = k / ng;
+  gk[t] = (unsigned long long)inst[b] * ng + (k - b * ng);
+  idx[t] = (int)t;
+}
+
+hipError_t launch_group_keys(const unsigned long long* keys, int64_t n, unsigned long long ng,
+                             const int* inst, unsigned long long* gk, int* idx,
+                             hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  group_key_kernel<<<nblk(n, 256), 256, 0, st>>>(keys, n, ng, inst, gk, idx);
+  return hipGetLastError();
+}
+
+// Stable radix sort of (64-bit key, int) pairs (rocPRIM): equal keys keep
+// their input order.  With scratch == nullptr only the scratch size is
+// returned.
+hipError_t sort_pairs(const unsigned long long* keys_in, unsigned long long* keys_out,
+                      const int* vals_in, int* vals_out, int64_t n, int end_bit, void* scratch,
+                      size_t* scratch_bytes, hipStream_t st) {
+  return rocprim::radix_sort_pairs(scratch, *scratch_bytes, keys_in, keys_out, vals_in,
+                                   vals_out, (size_t)n, 0u, (unsigned)end_bit, st);
+}
+
 // Radix sort of 64-bit keys (rocPRIM).  With scratch == nullptr only the
 // scratch size is returned.
 hipError_t sort_keys(unsigned long long* keys, unsigned long long* tmp,
