@@ -23,8 +23,10 @@
 // identity).  Every pass is target-owned: no atomics in the apply.
 //
 // Precision: T = double (FP64 mode) or float (FP32-mixed mode: values,
-// Lagrange weights and contractions in FP32; geometry, cone selection and
-// the phase argument kappa*r reduction in FP64).
+// Lagrange weights, contractions and the phase factor's sine and cosine in
+// FP32; geometry, the radial cone, the angular cone decisions (side tests)
+// and the phase argument kappa*r reduction in FP64; the angular estimates
+// and local coordinates of the propagation's cone selection in FP32).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
