@@ -294,6 +294,9 @@ def main():
                     help="compact records of the other workloads: all, none, or a "
                          "comma-separated list of workload names")
     ap.add_argument("--config-steps", type=int, default=5)
+    ap.add_argument("--tune-cache", default=None,
+                    help="file that keeps the autotuner's per-level choices, so that "
+                         "profiled runs of one workload plan the same kernels")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported",
@@ -332,13 +335,19 @@ def main():
         if batch:
             pl = ifgf.plan_batched([x.points for x in insts], [x.kappa for x in insts],
                                    p_s=p_s, p_ang=p_ang, precision=prec, n_rhs=n_rhs,
-                                   autotune=True, **popts)
+                                   autotune=True, tune_cache=args.tune_cache, **popts)
         else:
             pl = ifgf.plan(w.points, w.kappa, p_s=p_s, p_ang=p_ang, precision=prec,
-                           n_rhs=n_rhs, autotune=True, **popts)
+                           n_rhs=n_rhs, autotune=True, tune_cache=args.tune_cache, **popts)
         plan_s = time.perf_counter() - t0
-        print(f"# {prec}: plan {plan_s:.2f} s (N={n}, D={pl.info()['D']})",
-              file=sys.stderr, flush=True)
+        pi = pl.info()
+        print(f"# {prec}: plan {plan_s:.2f} s (N={n}, D={pi['D']})", file=sys.stderr, flush=True)
+        # Work units per apply, by level: the algorithmic counts behind
+        # per-kernel rates computed from a profiler's trace.
+        print(f"# {prec}: units " + json.dumps(
+            {k: pi[k] for k in ("boxes", "cones", "cousin_pairs", "prop_pairs", "prop_mode",
+                                "leaf_pairs", "near_pairs", "tune_cache_hit")}),
+            file=sys.stderr, flush=True)
         dt = torch.complex128 if prec == "fp64" else torch.complex64
         a = torch.from_numpy(dens).to(dt).cuda()
         ms_eager, _ = time_applies(pl, a, args.steps, args.warmup, graph=False)
