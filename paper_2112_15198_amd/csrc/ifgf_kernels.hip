@@ -610,9 +610,12 @@ interp_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ V,
 // cone, node p), one wave per block, with the child cone values staged in
 // LDS: per child octant the lanes' child cones are collected (wave ballots;
 // the nodes of a parent cone fall into few child cones), up to kNodeBufs of
-// them are copied into LDS with contiguous loads, and each lane contracts its
-// cone's values from there (from global memory beyond kNodeBufs).
+// them are copied into LDS with contiguous loads, kNodeStageBatch cones'
+// loads in flight together (one memory latency per batch instead of per
+// cone), and each lane contracts its cone's values from there (from global
+// memory beyond kNodeBufs).
 static constexpr int kNodeBufs = 8;
+static constexpr int kNodeStageBatch = 2;
 
 template <int PS, int PA, typename T, int MAXR>
 __global__ void __launch_bounds__(64)
@@ -687,20 +690,42 @@ prop_node_kernel(ApplyArgs A, int l, const typename C2<T>::type* __restrict__ Vc
       gc *= amp;
       gs *= amp;
     }
-    // Stage the distinct child cones of the wave in LDS.
+    // Stage the distinct child cones of the wave in LDS: collect them with
+    // ballots (lane q keeps the slot of the q-th), then copy them
+    // kNodeStageBatch cones at a time with all their loads in flight
+    // (clamped indices: every load is in bounds; stores past the end are
+    // skipped).
     unsigned long long pend = __ballot(cslot >= 0);
     if (pend == 0ull) continue;
-    int buf = -1, nb = 0;
+    int buf = -1, nb = 0, qslot = -1;
     while (pend) {
       const int c = __shfl(cslot, __ffsll((long long)pend) - 1);
       const bool mine = cslot == c;
       if (nb < kNodeBufs) {
-        const CT* src = Vc + (int64_t)c * nrhs * P;
-        for (int i = lane; i < nrhs * P; i += 64) s_v[nb][i] = src[i];
+        if (lane == nb) qslot = c;
         if (mine) buf = nb;
         ++nb;
       }
       pend &= ~__ballot(mine);
+    }
+    {
+      constexpr int NCH = (MAXR * P + 63) / 64;  // lane-strided chunks per cone
+      constexpr int QB = MAXR == 1 ? kNodeStageBatch : 1;
+      const int len = nrhs * P;
+      for (int q0 = 0; q0 < nb; q0 += QB) {
+        CT tmp[QB][NCH];
+#pragma unroll
+        for (int qq = 0; qq < QB; ++qq) {
+          const CT* src = Vc + (int64_t)__shfl(qslot, min(q0 + qq, nb - 1)) * len;
+#pragma unroll
+          for (int h = 0; h < NCH; ++h) tmp[qq][h] = src[min(h * 64 + lane, len - 1)];
+        }
+#pragma unroll
+        for (int qq = 0; qq < QB; ++qq)
+#pragma unroll
+          for (int h = 0; h < NCH; ++h)
+            if (q0 + qq < nb && h * 64 + lane < len) s_v[q0 + qq][h * 64 + lane] = tmp[qq][h];
+      }
     }
     __syncthreads();  // one wave: the LDS copies are complete
     if (cslot >= 0) {
