@@ -162,3 +162,30 @@ def test_bench_refuses_several_gpus():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU only" in r.stdout
+
+
+def test_bench_traffic_record_follows_the_kernel_source(tmp_path, monkeypatch):
+    """bench.py reports the rocprofv3 HBM traffic of the dominant kernel only
+    while the committed record's SHA-256 matches the kernel source; after any
+    change to the source it reports none (null) until the counters are
+    taken again."""
+    import hashlib
+    import json
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    src_dir = tmp_path / "paper_2112_15198_amd" / "csrc"
+    src_dir.mkdir(parents=True)
+    (tmp_path / "profiles").mkdir()
+    src = src_dir / "ifgf_kernels.hip"
+    src.write_text("// kernel source\n")
+    rec = {"stage": "propagation_small", "workload": "sphere_321k", "precision": "fp32",
+           "kernel_source_sha256": hashlib.sha256(src.read_bytes()).hexdigest(),
+           "traffic_bytes_per_launch": 123456789}
+    (tmp_path / "profiles" / "k_traffic.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("propagation_small", "sphere_321k", "fp32") == 123456789
+    assert bench.measured_traffic("propagation_small", "sphere_321k", "fp64") is None
+    assert bench.measured_traffic("interpolation", "sphere_321k", "fp32") is None
+    src.write_text("// kernel source, changed\n")
+    assert bench.measured_traffic("propagation_small", "sphere_321k", "fp32") is None
