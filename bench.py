@@ -271,7 +271,7 @@ def run_configs(steps, warmup, names=None):
     return recs
 
 
-def main():
+def arg_parser():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -297,7 +297,11 @@ def main():
     ap.add_argument("--tune-cache", default=None,
                     help="file that keeps the autotuner's per-level choices, so that "
                          "profiled runs of one workload plan the same kernels")
-    args = ap.parse_args()
+    return ap
+
+
+def main():
+    args = arg_parser().parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported",
               flush=True)

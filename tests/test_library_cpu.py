@@ -189,3 +189,24 @@ def test_bench_traffic_record_follows_the_kernel_source(tmp_path, monkeypatch):
     assert bench.measured_traffic("interpolation", "sphere_321k", "fp32") is None
     src.write_text("// kernel source, changed\n")
     assert bench.measured_traffic("propagation_small", "sphere_321k", "fp32") is None
+
+
+def test_profile_commands_are_valid_bench_invocations():
+    """Every bench.py command quoted in profiles/*.md parses with bench.py's
+    own argument parser and names a known workload, so the committed
+    summaries can be reproduced as written."""
+    import glob
+    import shlex
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    ap = bench.arg_parser()
+    found = 0
+    for f in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
+        text = open(f).read()
+        for m in re.finditer(r'python3 \$R/bench\.py([^"`\n]*)', text):
+            argv = shlex.split(m.group(1).replace("$R", "/tmp/r").replace("\\", ""))
+            args = ap.parse_args(argv)
+            assert args.workload in W.WORKLOADS, (f, args.workload)
+            found += 1
+    assert found >= 10
