@@ -197,7 +197,8 @@ ifgf_status ifgf_plan_ex(ifgf_plan_t* plan, const double* points, int64_t n,
 /* Plan n_inst independent instances evaluated together by every apply
  * (each kernel launch processes all instances): the batched form of the
  * operator of eq. (field1), one independent sum per instance.  Instance i owns points
- * [offsets[i], offsets[i+1]) of the host array `points` (offsets has n_inst+1
+ * [offsets[i], offsets[i+1]) of `points` (host or device memory, as for
+ * ifgf_plan; offsets, a host array, has n_inst+1
  * entries, offsets[0] = 0), wavenumber kappas[i].  Densities and outputs of
  * a batched apply are [n_rhs][N_total], N_total = offsets[n_inst], in that
  * concatenated order.  Interactions never cross instances. */
